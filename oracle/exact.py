@@ -1,0 +1,203 @@
+"""Exact densities of states for small lattices -- TEST INFRASTRUCTURE ONLY.
+
+These are the truth sources the oracle is pinned against (the paper compares its
+2D Ising results with exact ones, in the paragraph on the Ising and Potts tests):
+
+* ``brute_dos``: enumeration of every configuration (Ising, q-state Potts and
+  +-J models on L x L tori with at most a few million states).
+* ``ising_dos_transfer``: the 2D Ising DOS on an L x L torus by a row-to-row
+  transfer matrix over polynomials in the number of unsatisfied bonds, in exact
+  integer arithmetic (independent of the closed form below).
+* ``ising_dos_exact``: the 2D Ising DOS on an L x L torus (L even) from
+  Kaufman's closed-form partition function of the finite torus (B. Kaufman,
+  Phys. Rev. 76, 1232 (1949)), turned into the integer coefficients g(E) the way
+  P. D. Beale did (Phys. Rev. Lett. 76, 78 (1996)): Z is evaluated at M = N+1
+  points on the unit circle of x = exp(-4K) and the polynomial coefficients are
+  recovered by an inverse discrete Fourier transform, in high precision.
+
+Energies are E = -sum over bonds; the Ising DOS is returned over
+E = -2N, -2N+4, ..., 2N (N+1 entries).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _bonds(L):
+    """(site, right neighbour) and (site, lower neighbour) index arrays."""
+    idx = np.arange(L * L).reshape(L, L)
+    right = np.roll(idx, -1, axis=1).ravel()
+    down = np.roll(idx, -1, axis=0).ravel()
+    return idx.ravel(), right, down
+
+
+def brute_dos(model, L, q=2, couplings=None):
+    """Exact DOS by enumerating all configurations.
+
+    model: 'ising' | 'potts' | 'ea'.  couplings (ea): int8 array of 2N values,
+    [2i] = J(i, right), [2i+1] = J(i, down).  Returns a dict {E: count}.
+    """
+    N = L * L
+    nstates = 2 if model in ("ising", "ea") else q
+    total = nstates ** N
+    if total > 50_000_000:
+        raise ValueError("too many states for enumeration")
+    site, right, down = _bonds(L)
+    if model == "ea":
+        J = np.asarray(couplings, dtype=np.int64).reshape(N, 2)
+    counts = {}
+    chunk = 1 << 20
+    for start in range(0, total, chunk):
+        codes = np.arange(start, min(total, start + chunk), dtype=np.int64)
+        digits = np.empty((codes.size, N), dtype=np.int64)
+        c = codes.copy()
+        for i in range(N):
+            digits[:, i] = c % nstates
+            c //= nstates
+        if model == "potts":
+            E = -((digits[:, site] == digits[:, right]).sum(1)
+                  + (digits[:, site] == digits[:, down]).sum(1))
+        else:
+            s = 2 * digits - 1
+            if model == "ising":
+                E = -((s[:, site] * s[:, right]).sum(1) + (s[:, site] * s[:, down]).sum(1))
+            else:
+                E = -((J[:, 0] * s[:, site] * s[:, right]).sum(1)
+                      + (J[:, 1] * s[:, site] * s[:, down]).sum(1))
+        vals, cnt = np.unique(E, return_counts=True)
+        for v, n in zip(vals.tolist(), cnt.tolist()):
+            counts[v] = counts.get(v, 0) + n
+    return counts
+
+
+def ising_dos_transfer(L):
+    """Exact 2D Ising DOS on the L x L torus by a row transfer matrix.
+
+    Each row state is an L-bit integer; a polynomial in y counts unsatisfied
+    bonds.  Rows are added one by one from a fixed first row, and the periodic
+    closure with the first row is added at the end.  Python integers are exact.
+    Returns a list over E = -2N, -2N+4, ..., 2N.
+    """
+    N = L * L
+    nrow = 1 << L
+    rows = [[1 if (s >> c) & 1 else -1 for c in range(L)] for s in range(nrow)]
+    intra = [sum(rows[s][c] != rows[s][(c + 1) % L] for c in range(L)) for s in range(nrow)]
+    inter = [[sum(rows[a][c] != rows[b][c] for c in range(L)) for b in range(nrow)]
+             for a in range(nrow)]
+    D = 2 * N + 1
+    total = [0] * D
+    for s0 in range(nrow):
+        vec = {s0: {intra[s0]: 1}}
+        for _ in range(L - 1):
+            new = {}
+            for a, poly in vec.items():
+                for b in range(nrow):
+                    add = inter[a][b] + intra[b]
+                    tgt = new.setdefault(b, {})
+                    for u, n in poly.items():
+                        tgt[u + add] = tgt.get(u + add, 0) + n
+            vec = new
+        for a, poly in vec.items():
+            add = inter[a][s0]
+            for u, n in poly.items():
+                total[u + add] += n
+    # E = -2N + 2u; the number u of unsatisfied bonds is even on the torus
+    out = []
+    for j in range(N + 1):
+        out.append(total[2 * j])
+    assert all(total[u] == 0 for u in range(1, D, 2))
+    return out
+
+
+def ising_dos_exact(L, extra_digits=40):
+    """Exact 2D Ising DOS on the L x L torus (L even) from Kaufman's formula.
+
+    Z(K) = 1/2 (2 sinh 2K)^(N/2) (Z1 + Z2 + Z3 + Z4) with, for L even,
+      Z1 = prod_{k odd < L} 2 (T_L(c_k) + 1),  Z2 = prod_{k odd < L} 2 (T_L(c_k) - 1),
+      Z3 = 2cosh(L g0/2) 2cosh(L gL/2) prod_{k even, 0<k<L} 2 (T_L(c_k) + 1),
+      Z4 = 2sinh(L g0/2) 2sinh(L gL/2) prod_{k even, 0<k<L} 2 (T_L(c_k) - 1),
+    where c_k = cosh 2K coth 2K - cos(pi k / L) is cosh(gamma_k), T_L is the
+    Chebyshev polynomial (cosh(L gamma) = T_L(cosh gamma)), and the two unpaired
+    factors use exp(g0) = exp(2K) tanh K and exp(gL) = exp(2K) / tanh K.  The
+    products over k and 2L-k coincide, which is why they appear squared, and
+    every factor is then an entire function of K without branch choices.
+    P(x) = exp(-2NK) Z is a polynomial of degree N in x = exp(-4K) whose
+    coefficient j is g(E = -2N + 4j); it is sampled at x_m = exp(2 pi i (m+1/2)/M),
+    M = N + 1, and inverted by a DFT.  Returns a list of Python ints.
+    """
+    import mpmath as mp
+
+    if L % 2:
+        raise ValueError("L must be even")
+    N = L * L
+    M = N + 1
+    with mp.workdps(int(N * 0.30103) + extra_digits):
+        cos_k = [mp.cos(mp.pi * k / L) for k in range(L + 1)]
+
+        def cheb(c):
+            t0, t1 = mp.mpf(1), c
+            for _ in range(L - 1):
+                t0, t1 = t1, 2 * c * t1 - t0
+            return t1
+
+        values = []
+        for m in range(M):
+            theta = 2 * mp.pi * (m + mp.mpf(1) / 2) / M
+            K = mp.mpc(0, -theta / 4)
+            s2 = mp.sinh(2 * K)
+            ch2 = mp.cosh(2 * K)
+            base = ch2 * ch2 / s2
+            t = mp.tanh(K)
+            eLK = mp.exp(L * K)
+            th = t ** (L // 2)
+            e0 = eLK * th          # exp(L g0 / 2)
+            eL = eLK / th          # exp(L gL / 2)
+            z1 = z2 = mp.mpc(1)
+            z3 = (e0 + 1 / e0) * (eL + 1 / eL)
+            z4 = (e0 - 1 / e0) * (eL - 1 / eL)
+            for k in range(1, L):
+                T = cheb(base - cos_k[k])
+                if k % 2:
+                    z1 *= 2 * (T + 1)
+                    z2 *= 2 * (T - 1)
+                else:
+                    z3 *= 2 * (T + 1)
+                    z4 *= 2 * (T - 1)
+            Z = (2 * s2) ** (N // 2) * (z1 + z2 + z3 + z4) / 2
+            values.append(mp.exp(-2 * N * K) * Z)
+        # x_m^-j = exp(-i pi (2m+1) j / M): one table of the 2M-th roots of unity
+        roots = [mp.expjpi(-mp.mpf(r) / M) for r in range(2 * M)]
+        out = []
+        worst = mp.mpf(0)
+        for j in range(M):
+            acc = mp.mpc(0)
+            for m in range(M):
+                acc += values[m] * roots[((2 * m + 1) * j) % (2 * M)]
+            acc /= M
+            n = int(mp.nint(acc.real))
+            err = abs(acc - n)
+            if err > worst:
+                worst = err
+            out.append(n)
+        if worst > 1e-6:
+            raise ArithmeticError(f"DFT residue {worst} too large; raise extra_digits")
+    return out
+
+
+def ln_dos(counts_by_e):
+    """{E: count} or list -> (E array, ln g array) over the nonzero entries."""
+    import math
+
+    items = sorted(counts_by_e.items())
+    E = np.array([e for e, n in items if n > 0], dtype=np.int64)
+    lg = np.array([math.log(n) for e, n in items if n > 0])
+    return E, lg
+
+
+def ising_list_to_dict(L, g):
+    N = L * L
+    return {-2 * N + 4 * j: n for j, n in enumerate(g)}
+
+
+__all__ = ["brute_dos", "ising_dos_transfer", "ising_dos_exact", "ln_dos",
+           "ising_list_to_dict"]

@@ -1,0 +1,498 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU needed).
+
+Each test checks a piece of the oracle against the mathematics, an exact
+enumeration, an independent library, or an exact density of states, so that a
+dropped term, a wrong sign or a swapped index in the oracle fails one of them.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, load_ising_golden
+
+
+# ------------------------------------------------------------------ Philox --
+def test_philox_matches_rocrand(oracle_lib, tmp_path):
+    """Philox4x32-10 (Salmon et al., SC'11) agrees with rocRAND's implementation.
+
+    rocRAND keeps counter = (offset/4, subsequence) and key = seed, so the oracle's
+    block for counter (t_lo, t_hi, walker, stream) is rocRAND's four draws after
+    rocrand_init(seed, walker | stream << 32, 4 t)."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND probe")
+    exe = tmp_path / "anchor"
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-o", str(exe),
+                    os.path.join(ROOT, "tests", "rocrand_anchor.hip")], check=True)
+    rng = np.random.default_rng(5)
+    cases = []
+    for _ in range(200):
+        seed = int(rng.integers(0, 2 ** 63))
+        t = int(rng.integers(0, 2 ** 40))
+        walker = int(rng.integers(0, 2 ** 32))
+        stream = int(rng.integers(0, 8))
+        cases.append((seed, t, walker, stream))
+    cases += [(0, 0, 0, 0), (2 ** 64 - 1, 2 ** 62 - 1, 2 ** 32 - 1, 3)]
+    inp = "\n".join(f"{s} {w | (st << 32)} {4 * t}" for s, t, w, st in cases) + "\n"
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True)
+    got = [list(map(int, line.split())) for line in out.stdout.strip().splitlines()]
+    for (seed, t, w, st), ref in zip(cases, got):
+        ours = oracle_lib.philox([t & 0xFFFFFFFF, t >> 32, w, st],
+                                 [seed & 0xFFFFFFFF, seed >> 32])
+        assert list(map(int, ours)) == ref, (seed, t, w, st)
+
+
+def test_philox_counter_sensitivity(oracle_lib):
+    base = oracle_lib.philox([1, 2, 3, 4], [5, 6])
+    for i in range(4):
+        c = [1, 2, 3, 4]
+        c[i] ^= 1
+        assert not np.array_equal(oracle_lib.philox(c, [5, 6]), base)
+
+
+# ------------------------------------------------------------- uniform, ln --
+def test_uniform_range(oracle_lib):
+    assert oracle_lib.uniform(0, 0) == 2.0 ** -53
+    assert oracle_lib.uniform(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    assert oracle_lib.uniform(0x80000000, 0) == 0.5 + 2.0 ** -53
+    # the low 12 bits of the second word are unused
+    assert oracle_lib.uniform(123, 0xFFF) == oracle_lib.uniform(123, 0)
+
+
+def _ulp(x):
+    return math.ulp(x)
+
+
+def test_ln_u_accuracy(oracle_lib):
+    """ln u within 2 ulp of the exact logarithm (mpmath, 40 digits) over (0,1)."""
+    import mpmath as mp
+
+    rng = np.random.default_rng(11)
+    hi = rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64)
+    lo = rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64)
+    us = [oracle_lib.uniform(int(a), int(b)) for a, b in zip(hi, lo)]
+    us += [0.5 + 2.0 ** -53, 1 - 2.0 ** -53, 2.0 ** -53, 1 / math.sqrt(2),
+           math.sqrt(2) / 2 + 1e-16, 0.75, 0.25, 1e-10, 0.999999]
+    us += list(np.exp(-rng.uniform(0, 36, 2000)))
+    worst = 0.0
+    with mp.workdps(40):
+        for u in us:
+            ref = mp.log(mp.mpf(u))
+            got = oracle_lib.ln_u(u)
+            err = abs(mp.mpf(got) - ref) / _ulp(float(ref))
+            worst = max(worst, float(err))
+            assert got < 0.0
+    assert worst <= 2.0, worst
+
+
+def test_ln_u_monotone(oracle_lib):
+    xs = np.sort(np.random.default_rng(3).uniform(1e-12, 1 - 1e-12, 3000))
+    ys = [oracle_lib.ln_u(float(x)) for x in xs]
+    assert all(a <= b for a, b in zip(ys, ys[1:]))
+
+
+def test_ln2_split_constants():
+    """The two halves of ln 2 used by ln u: 32 fractional bits, then the rest."""
+    import mpmath as mp
+
+    src = open(os.path.join(ROOT, "oracle", "rewl_oracle.c")).read()
+    hi = float.fromhex(src.split("LN2_HI = ")[1].split(";")[0])
+    lo = float.fromhex(src.split("LN2_LO = ")[1].split(";")[0])
+    with mp.workdps(50):
+        ln2 = mp.log(2)
+        assert hi == float(mp.nint(ln2 * 2 ** 32) / 2 ** 32)
+        assert lo == float(ln2 - mp.mpf(hi))
+
+
+# ------------------------------------------------------------------ models --
+def test_energy_reference_states(oracle_lib):
+    L = 6
+    N = L * L
+    up = np.ones(N, dtype=np.int8)
+    chk = np.array([1 if (i // L + i % L) % 2 == 0 else -1 for i in range(N)], dtype=np.int8)
+    assert oracle_lib.energy("ising", L, up) == -2 * N
+    assert oracle_lib.energy("ising", L, chk) == 2 * N
+    assert oracle_lib.energy("potts", L, np.zeros(N, np.int8), q=3) == -2 * N
+    stripes = np.array([i % 3 for i in range(N)], dtype=np.int8)  # rows alike, columns differ
+    assert oracle_lib.energy("potts", L, stripes, q=3) == -N
+    J = -np.ones(2 * N, dtype=np.int8)
+    assert oracle_lib.energy("ea", L, up, J) == 2 * N
+    # one flipped spin in the ferromagnet costs 8
+    one = up.copy()
+    one[7] = -1
+    assert oracle_lib.energy("ising", L, one) == -2 * N + 8
+
+
+def test_energy_matches_brute_force_definition(oracle_lib):
+    """orc_energy against an independent numpy bond sum on random states."""
+    from workloads import ea_couplings
+
+    rng = np.random.default_rng(2)
+    for L in (3, 4, 7):
+        N = L * L
+        idx = np.arange(N).reshape(L, L)
+        rt = np.roll(idx, -1, 1).ravel()
+        dn = np.roll(idx, -1, 0).ravel()
+        J = ea_couplings(L, L).astype(np.int64).reshape(N, 2)
+        for _ in range(20):
+            s = rng.choice([-1, 1], N).astype(np.int8)
+            si = s.astype(np.int64)
+            assert oracle_lib.energy("ising", L, s) == -(si * si[rt] + si * si[dn]).sum()
+            assert oracle_lib.energy("ea", L, s, J.ravel().astype(np.int8)) == \
+                -(J[:, 0] * si * si[rt] + J[:, 1] * si * si[dn]).sum()
+            p = rng.integers(0, 5, N).astype(np.int8)
+            assert oracle_lib.energy("potts", L, p, q=5) == -((p == p[rt]).sum() + (p == p[dn]).sum())
+
+
+@pytest.mark.parametrize("model,q", [("ising", 2), ("potts", 4), ("ea", 2)])
+def test_walker_energy_tracks_spins(oracle_lib, model, q):
+    """After rounds of sweeps and exchanges every walker's E equals E(spins)."""
+    from workloads import ea_couplings
+
+    L = 6
+    J = ea_couplings(L, 3) if model == "ea" else None
+    run = oracle_lib.Run(model, L, q=q, couplings=J, n_windows=3, walkers_per_window=2,
+                         S=500, seed=9)
+    for _ in range(5):
+        run.step(3)
+        for w in range(run.h * run.m):
+            st = run.walker(w)
+            assert st["E"] == oracle_lib.energy(model, L, st["spins"], J, q=q)
+            win = run.window(w // run.m)
+            b = (st["E"] - run.e_min) // run.e_step
+            assert win["lo"] <= b <= win["hi"]
+            if model == "potts":
+                assert st["spins"].min() >= 0 and st["spins"].max() < q
+            else:
+                assert set(np.unique(st["spins"])) <= {-1, 1}
+
+
+# --------------------------------------------------------------- partition --
+def test_partition_examples(oracle_lib):
+    lo, hi = oracle_lib.partition(65, 4, 0.75)          # 8x8 Ising
+    assert list(zip(lo, hi)) == [(0, 37), (9, 46), (18, 55), (27, 64)]
+    lo, hi = oracle_lib.partition(1025, 16, 0.75)       # 32x32 Ising
+    assert (hi - lo + 1).max() == 218 and lo[0] == 0 and hi[-1] == 1024
+    assert (hi[:-1] - lo[1:] + 1).min() >= 163
+    lo, hi = oracle_lib.partition(8193, 32, 0.75)       # 64x64 Potts
+    assert (hi - lo + 1).max() == 939
+
+
+def test_partition_invariants(oracle_lib):
+    for B in (20, 65, 257, 1025, 4097):
+        for h in (1, 2, 3, 5, 8, 16):
+            for o in (0.5, 0.75, 0.9):
+                try:
+                    lo, hi = oracle_lib.partition(B, h, o)
+                except ValueError:
+                    continue
+                assert lo[0] == 0 and hi[-1] == B - 1
+                assert np.all(np.diff(lo) > 0) and np.all(np.diff(hi) >= 0)
+                assert np.all(hi[:-1] >= lo[1:] + 1)         # overlap of at least 2 bins
+                covered = np.zeros(B, bool)
+                for a, b in zip(lo, hi):
+                    covered[a:b + 1] = True
+                assert covered.all()
+
+
+# ---------------------------------------------------------- exact DOS tools --
+def test_exact_ising_three_ways():
+    """Kaufman's closed form = transfer matrix = enumeration (L = 4); L = 6 = transfer."""
+    from oracle import exact
+
+    g4 = exact.ising_dos_exact(4)
+    brute = exact.brute_dos("ising", 4)
+    assert g4 == [brute.get(-32 + 4 * j, 0) for j in range(17)]
+    assert g4 == exact.ising_dos_transfer(4)
+    assert exact.ising_dos_exact(6) == exact.ising_dos_transfer(6)
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_exact_ising_golden_sum_rules(L):
+    """Golden tables: sum 2^N, g(E) = g(-E), and the low-energy counts 2, 0, 2N, 4N."""
+    path = os.path.join(ROOT, "tests", "golden", f"ising_exact_L{L}.txt")
+    g = [int(line.split()[1]) for line in open(path) if not line.startswith("#")]
+    N = L * L
+    assert sum(g) == 2 ** N
+    assert g == g[::-1]
+    assert g[0] == 2 and g[1] == 0 and g[2] == 2 * N and g[3] == 4 * N
+
+
+def test_exact_ising_golden_L8_regenerates():
+    from oracle import exact
+
+    path = os.path.join(ROOT, "tests", "golden", "ising_exact_L8.txt")
+    g = [int(line.split()[1]) for line in open(path) if not line.startswith("#")]
+    assert g == exact.ising_dos_exact(8)
+
+
+def test_exact_ising_golden_L32_shape():
+    E, lg = load_ising_golden(32)
+    N = 1024
+    assert len(E) == N + 1 and E[0] == -2 * N
+    assert abs(lg[0] - math.log(2)) < 1e-15 and lg[1] == -math.inf
+    assert abs(lg[2] - math.log(2 * N)) < 1e-12 and abs(lg[3] - math.log(4 * N)) < 1e-12
+    fin = np.isfinite(lg)
+    rev = lg[::-1]
+    assert np.array_equal(np.isfinite(rev), fin)
+    assert np.allclose(lg[fin], rev[fin], atol=1e-12)
+    # sum g = 2^N
+    mx = lg[fin].max()
+    assert abs(mx + math.log(np.exp(lg[fin] - mx).sum()) - N * math.log(2)) < 1e-9
+
+
+def test_brute_force_potts_q2_is_ising():
+    """delta(s,s') = (1 + s s')/2 gives E_Potts = -N + E_Ising / 2 at q = 2."""
+    from oracle import exact
+
+    ising = exact.brute_dos("ising", 4)
+    potts = exact.brute_dos("potts", 4, q=2)
+    assert potts == {-16 + e // 2: n for e, n in ising.items()}
+
+
+def test_brute_force_potts_counts():
+    from oracle import exact
+
+    L, q = 3, 3
+    N = L * L
+    g = exact.brute_dos("potts", L, q=q)
+    assert sum(g.values()) == q ** N
+    assert g[-2 * N] == q
+    assert all(g.get(-2 * N + d, 0) == 0 for d in (1, 2, 3))
+    assert g[-2 * N + 4] == q * N * (q - 1)
+
+
+def test_brute_force_ea_symmetry():
+    """On an even torus g(E) = g(-E) for any +-J couplings (flip one sublattice)."""
+    from oracle import exact
+    from workloads import ea_couplings
+
+    J = ea_couplings(4, 1)
+    g = exact.brute_dos("ea", 4, couplings=J)
+    assert sum(g.values()) == 2 ** 16
+    assert all(g[e] == g.get(-e, 0) for e in g)
+    n_neg = int((J < 0).sum())
+    assert all((e - (-32 + 2 * n_neg)) % 4 == 0 for e in g)
+
+
+# --------------------------------------------------------------- stitching --
+def test_stitch_recovers_exact_pieces(oracle_lib):
+    """Exact ln g pieces with arbitrary offsets are joined back to ln g + const."""
+    E, lg = load_ising_golden(16)
+    B = len(lg)
+    lo, hi = oracle_lib.partition(B, 6, 0.75)
+    W = int((hi - lo + 1).max())
+    P = np.zeros((6, W))
+    V = np.zeros((6, W), np.uint8)
+    rng = np.random.default_rng(4)
+    for k in range(6):
+        seg = lg[lo[k]:hi[k] + 1]
+        fin = np.isfinite(seg)
+        P[k, :len(seg)][fin] = seg[fin] + rng.uniform(-50, 50)
+        V[k, :len(seg)] = fin
+    out, joins = oracle_lib.stitch(lo, hi, P, V, B)
+    fin = np.isfinite(lg)
+    assert np.array_equal(np.isfinite(out), fin)
+    d = out[fin] - lg[fin]
+    assert d.max() - d.min() < 1e-9
+    for k, j in enumerate(joins):
+        assert lo[k + 1] <= j <= hi[k]
+
+
+def test_stitch_picks_matching_slope(oracle_lib):
+    """Where the two pieces agree in slope only at one place, the join is there."""
+    B = 12
+    lo = np.array([0, 4])
+    hi = np.array([7, 11])
+    base = np.arange(B, dtype=float) ** 1.5
+    P = np.zeros((2, 8))
+    P[0] = base[0:8]
+    P[1] = base[4:12] + 3.0
+    P[1, 0:2] += np.array([5.0, 0.0])   # bin 4 disagrees in slope with piece 0
+    P[1, 3] += 7.0                      # slopes around bin 7 disagree too
+    V = np.ones((2, 8), np.uint8)
+    out, joins = oracle_lib.stitch(lo, hi, P, V, B)
+    assert joins[0] == 5
+    assert np.allclose(out[:5], base[:5]) and np.allclose(out[5:7], base[5:7])
+
+
+# ------------------------------------------------------- Markov-chain pins --
+def _fixed_weight_run(oracle_lib, lg_exact, tilt, h, m, S, seed, L=4):
+    """Walkers with ln g frozen at exact + tilt * E: visits must follow exp(-tilt E)."""
+    run = oracle_lib.Run("ising", L, n_windows=h, overlap=0.75, walkers_per_window=m,
+                         flatness=1.0, lnf_init=1e-300, lnf_final=1e-310, S=S, seed=seed)
+    E = run.energies()
+    for w in range(h * m):
+        win = run.window(w // m)
+        seg = slice(win["lo"], win["hi"] + 1)
+        vals = lg_exact[seg] + tilt[w // m] * E[seg]
+        vals = np.where(np.isfinite(vals), vals - np.nanmin(np.where(np.isfinite(vals), vals, np.nan)) + 1.0, 0.0)
+        run.set_lng(w, vals)
+    return run, E
+
+
+def test_sweep_samples_inverse_dos(oracle_lib):
+    """With ln g fixed at the exact DOS the energy histogram is flat (A1, A3)."""
+    from oracle import exact
+
+    g = exact.ising_dos_exact(4)
+    lg = np.array([math.log(x) if x else -np.inf for x in g])
+    for tilt in (0.0, 0.06):
+        run, E = _fixed_weight_run(oracle_lib, lg, [tilt], 1, 1, 20_000, 3)
+        run.step(100)
+        H = run.walker(0)["H"].astype(float)
+        reach = np.isfinite(lg)
+        target = np.exp(-tilt * E[reach])
+        target *= H[reach].sum() / target.sum()
+        rel = np.abs(H[reach] / target - 1.0)
+        assert rel.max() < 0.05, (tilt, rel.max())
+        assert H[~reach].sum() == 0
+
+
+def test_exchange_keeps_detailed_balance(oracle_lib):
+    """Frequent exchanges between tilted walkers keep each one's exp(-tilt E) law (Eq. (1))."""
+    from oracle import exact
+
+    g = exact.ising_dos_exact(4)
+    lg = np.array([math.log(x) if x else -np.inf for x in g])
+    tilts = [0.05, -0.05]
+    run, E = _fixed_weight_run(oracle_lib, lg, tilts, 2, 2, 20, 5)
+    run.step(100_000)
+    st = run.stats()
+    assert st["ex_acc"] > 0.05 * st["ex_prop"]
+    for w in range(4):
+        k = w // 2
+        win = run.window(k)
+        seg = slice(win["lo"], win["hi"] + 1)
+        H = run.walker(w)["H"].astype(float)
+        reach = np.isfinite(lg[seg])
+        target = np.exp(-tilts[k] * E[seg][reach])
+        target *= H[reach].sum() / target.sum()
+        rel = np.abs(H[reach] / target - 1.0)
+        # statistical scatter stays near 0.1; a sign error in Eq. (1) gives ~3
+        assert rel.max() < 0.25, (w, rel.max())
+
+
+# -------------------------------------------------------------- schedule --
+def test_merge_and_schedule(oracle_lib):
+    """Windows merge only when all m walkers are flat; ln f halves; H resets."""
+    run = oracle_lib.Run("ising", 6, n_windows=2, walkers_per_window=2, S=2000, seed=4,
+                         lnf_final=1e-3)
+    prev = [1.0, 1.0]
+    for _ in range(400):
+        run.step(1)
+        for k in range(2):
+            win = run.window(k)
+            sts = [run.walker(2 * k + s) for s in range(2)]
+            if win["lnf"] != prev[k]:
+                assert win["lnf"] == prev[k] * 0.5
+                assert np.array_equal(sts[0]["lng"], sts[1]["lng"])
+                assert np.array_equal(sts[0]["visited"], sts[1]["visited"])
+                if not win["done"]:
+                    # fresh iteration: only the exchange step ran after the merge
+                    assert all(s["H"].sum() == 0 for s in sts)
+                prev[k] = win["lnf"]
+            assert np.array_equal(sts[0]["visited"] > 0, sts[0]["lng"] > 0)
+        if run.info()["done"]:
+            break
+    assert run.info()["done"]
+    for k in range(2):
+        w = run.window(k)
+        assert w["done"] and w["lnf"] < 1e-3 <= 2 * w["lnf"]
+
+
+def test_histogram_counts_attempts(oracle_lib):
+    run = oracle_lib.Run("potts", 5, q=3, n_windows=3, walkers_per_window=2, S=777, seed=8)
+    run.step(1)
+    for w in range(6):
+        st = run.walker(w)
+        assert st["H"].sum() == 777 and st["t"] == 777
+
+
+def test_deterministic_and_thread_independent(oracle_lib):
+    from workloads import ea_couplings
+
+    J = ea_couplings(8, 2)
+    a = oracle_lib.Run("ea", 8, couplings=J, n_windows=4, walkers_per_window=2, S=3000, seed=6,
+                       n_threads=1)
+    b = oracle_lib.Run("ea", 8, couplings=J, n_windows=4, walkers_per_window=2, S=3000, seed=6,
+                       n_threads=4)
+    a.step(30)
+    b.step(30)
+    for w in range(8):
+        x, y = a.walker(w), b.walker(w)
+        for key in ("spins", "lng", "H", "visited"):
+            assert np.array_equal(x[key], y[key])
+        assert x["E"] == y["E"] and x["t"] == y["t"]
+
+
+def test_descent_reaches_every_window(oracle_lib):
+    """Start-up puts each walker inside its window, the lowest q=10 Potts windows
+    through the ordered-state restart."""
+    run = oracle_lib.Run("potts", 16, q=10, n_windows=8, walkers_per_window=2, seed=3)
+    for w in range(16):
+        st = run.walker(w)
+        win = run.window(w // 2)
+        b = (st["E"] - run.e_min) // run.e_step
+        assert win["lo"] <= b <= win["hi"]
+
+
+def test_invalid_arguments(oracle_lib):
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ising", 2)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("potts", 8, q=1)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ising", 8, overlap=1.0)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ising", 8, n_windows=40)   # windows narrower than 2 bins
+
+
+# ----------------------------------------------------- convergence to truth --
+def _max_err(lg, ref):
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(lg), fin)
+    return np.abs(lg[fin] - ref[fin]).max()
+
+
+def test_ising8_converges_to_exact(oracle_lib):
+    """Ising 8x8, 4 windows x 2 walkers, ln f 1 -> 1e-6: ln g within WL's
+    statistical error of the exact DOS, normalised ln g(-2N) = ln 2."""
+    _, ref = load_ising_golden(8)
+    errs = []
+    for seed in (1, 2, 3):
+        run = oracle_lib.Run("ising", 8, n_windows=4, walkers_per_window=2, lnf_final=1e-6,
+                             S=10_000, seed=seed)
+        assert run.run()
+        lg = run.lng()
+        assert lg[0] == math.log(2)
+        errs.append(_max_err(lg, ref))
+    assert max(errs) < 0.3, errs
+
+
+def test_small_models_converge_to_brute_force(oracle_lib):
+    """3x3 q=3 Potts and a 4x4 +-J glass against exact enumeration."""
+    from oracle import exact
+    from workloads import ea_couplings
+
+    g = exact.brute_dos("potts", 3, q=3)
+    run = oracle_lib.Run("potts", 3, q=3, n_windows=2, walkers_per_window=2, lnf_final=1e-6,
+                         S=5_000, seed=2)
+    assert run.run()
+    E = run.energies()
+    ref = np.array([math.log(g[e]) if g.get(e, 0) else -np.inf for e in E])
+    ref = ref - ref[0] + math.log(3)
+    assert _max_err(run.lng(), ref) < 0.25
+
+    J = ea_couplings(4, 1)
+    g = exact.brute_dos("ea", 4, couplings=J)
+    run = oracle_lib.Run("ea", 4, couplings=J, n_windows=2, walkers_per_window=2,
+                         lnf_final=1e-6, S=5_000, seed=2)
+    assert run.run()
+    E = run.energies()
+    ref = np.array([math.log(g[e]) if g.get(e, 0) else -np.inf for e in E])
+    assert _max_err(run.lng(), ref) < 0.25

@@ -1,0 +1,88 @@
+"""Seeded synthetic inputs shared by the tests and the benchmark.
+
+This module holds no part of the method's arithmetic: it only names the
+workloads (lattice model, size, windows, walkers, schedule) and draws the random
+inputs that are not part of the Monte Carlo itself -- the +-J couplings of the
+spin-glass instances and the arrival stream of the served workload -- from
+numpy's seeded generator.  The oracle and the GPU library both receive these as
+plain arrays and numbers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Workload parameters.  Energies: Ising and +-J span [-2N, 2N] in steps of 4,
+# Potts [-2N, 0] in steps of 1 (N = L*L).
+CONFIGS = {
+    # 2D Ising 8x8, 4 windows x 2 walkers, ln f 1 -> 1e-6 (the small parity case)
+    "ising8": dict(model="ising", L=8, q=2, n_windows=4, overlap=0.75, walkers_per_window=2,
+                   flatness=0.8, lnf_init=1.0, lnf_final=1e-6, S=10_000),
+    # 2D Ising 32x32, 16 windows x 4 walkers, exchange every 1e4 attempts, ln f final 1e-8
+    "ising32": dict(model="ising", L=32, q=2, n_windows=16, overlap=0.75, walkers_per_window=4,
+                    flatness=0.8, lnf_init=1.0, lnf_final=1e-8, S=10_000),
+    # 2D 10-state Potts 64x64, 32 windows x 8 walkers, ln f final 1e-8
+    "potts64": dict(model="potts", L=64, q=10, n_windows=32, overlap=0.75, walkers_per_window=8,
+                    flatness=0.8, lnf_init=1.0, lnf_final=1e-8, S=10_000),
+    # one 2D +-J Edwards-Anderson glass 24x24, 8 windows x 4 walkers (256 of them batched)
+    "ea24": dict(model="ea", L=24, q=2, n_windows=8, overlap=0.75, walkers_per_window=4,
+                 flatness=0.8, lnf_init=1.0, lnf_final=1e-6, S=10_000),
+}
+
+
+def ea_couplings(L, seed):
+    """+-1 couplings with p = 1/2, laid out [2i] = J(i, right), [2i+1] = J(i, down)."""
+    rng = np.random.default_rng(np.random.SeedSequence([0xEA, int(seed)]))
+    return np.where(rng.random(2 * L * L) < 0.5, 1, -1).astype(np.int8)
+
+
+def full_range(model, L):
+    N = L * L
+    return (-2 * N, 0) if model == "potts" else (-2 * N, 2 * N)
+
+
+def run_params(name, seed=1, **over):
+    """Complete parameter dict for a named workload (couplings drawn for EA)."""
+    p = dict(CONFIGS[name])
+    p.update(over)
+    e_min, e_max = full_range(p["model"], p["L"])
+    p.setdefault("e_min", e_min)
+    p.setdefault("e_max", e_max)
+    p["seed"] = int(seed)
+    if p["model"] == "ea" and "couplings" not in p:
+        p["couplings"] = ea_couplings(p["L"], seed)
+    elif p["model"] != "ea":
+        p["couplings"] = None
+    return p
+
+
+def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6)):
+    """Poisson arrivals of REWL requests with a mix of models and sizes.
+
+    Ising L in {16,24,32,48,64}; Potts q in 2..10, L in 16..48; +-J L in 16..32;
+    windows 4..32; walkers 2, 4 or 8 per window.  Returns a list of dicts with an
+    'arrival' time in seconds and the run parameters.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([0x5E, int(seed)]))
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        kind = ("ising", "potts", "ea")[rng.integers(3)]
+        if kind == "ising":
+            L = int(rng.choice([16, 24, 32, 48, 64]))
+            q = 2
+        elif kind == "potts":
+            L = int(rng.integers(16, 49))
+            q = int(rng.integers(2, 11))
+        else:
+            L = int(rng.integers(16, 33))
+            q = 2
+        h = int(rng.integers(4, 33))
+        m = int(rng.choice([2, 4, 8]))
+        e_min, e_max = full_range(kind, L)
+        p = dict(model=kind, L=L, q=q, n_windows=h, overlap=0.75, walkers_per_window=m,
+                 flatness=0.8, lnf_init=1.0, lnf_final=float(rng.choice(lnf_choices)),
+                 S=10_000, e_min=e_min, e_max=e_max, seed=1000 + i)
+        p["couplings"] = ea_couplings(L, 1000 + i) if kind == "ea" else None
+        out.append(dict(arrival=t, params=p))
+    return out
