@@ -1,0 +1,167 @@
+/*
+ * rewl.h -- C ABI of the MI355X (gfx950) replica-exchange Wang-Landau library.
+ *
+ * Method: Vogel, Li, Wuest & Landau, "A generic, hierarchical framework for
+ * massively parallel Wang-Landau sampling", arXiv:1305.5615.  The energy range
+ * is split into n_windows overlapping windows (overlap o), each sampled by
+ * walkers_per_window independent Wang-Landau walkers with their own ln g(E) and
+ * H(E) (the parallel-scheme paragraph after Fig. 1); moves are accepted with
+ * min[1, g(E_old)/g(E_new)] and ln g(E) += ln f, H(E) += 1 at the current
+ * energy after every move (the standard-WL paragraph); walkers of adjacent
+ * windows exchange configurations with the probability of Eq. (1); when all
+ * walkers of a window are flat their ln g are averaged and ln f is halved;
+ * the run ends when every window's ln f is below lnf_final, and the window
+ * pieces are joined where d ln g / dE agree best.
+ *
+ * Models on an L x L torus: REWL_ISING E = -sum s_i s_j (step 4),
+ * REWL_POTTS E = -sum delta(s_i, s_j) (q states, step 1), REWL_EA
+ * E = -sum J_ij s_i s_j with J = +-1 (step 4).
+ *
+ * Conventions for every function:
+ *  - return value: REWL_OK (0), REWL_NOT_CONVERGED (1, informational) or a
+ *    negative error code; rewl_last_error() then describes it (thread-local,
+ *    valid until the next call on the same thread);
+ *  - host pointers are read or written only during the call and stay owned by
+ *    the caller; the library copies what it keeps;
+ *  - a handle is used by one host thread at a time;
+ *  - all device work runs on the stream given at creation (NULL: the null
+ *    stream); functions that return host data synchronise that stream.
+ * Every step of the method runs in this library's HIP kernels (sweep, flatness
+ * and merge, exchange, start-up) except the final stitching, which is a host
+ * loop over at most a few thousand bins.
+ */
+#ifndef REWL_H
+#define REWL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    REWL_OK = 0,
+    REWL_NOT_CONVERGED = 1,
+    REWL_EINVAL = -1,   /* argument out of range or inconsistent */
+    REWL_ENOMEM = -2,   /* host or device allocation failed / buffer too small */
+    REWL_EDEVICE = -3,  /* a HIP call failed */
+    REWL_EINIT = -4,    /* a walker could not be brought into its window */
+    REWL_ECORRUPT = -5, /* state failed a consistency check */
+    REWL_EBUSY = -6,    /* server has no free capacity */
+    REWL_ESTITCH = -7   /* a window overlap holds no commonly visited bin */
+};
+
+enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2 };
+
+/* Parameters of one run.
+ *  couplings: REWL_EA only, 2*L*L values +-1, [2i] = J(i, right neighbour),
+ *             [2i+1] = J(i, lower neighbour), site i = row*L + column; else NULL.
+ *  e_min, e_max: inclusive energy range; clipped to the model's range and, for
+ *             REWL_EA, aligned inwards onto the energy class -2N + 2 n_neg (mod 4)
+ *             of the couplings.
+ *  n_windows >= 1, 0 < overlap < 1, walkers_per_window in [1, 64],
+ *  0 < flatness <= 1, lnf_init > 0, lnf_final > 0,
+ *  attempts_per_round >= 1 (attempts per walker between exchange steps),
+ *  seed: Philox4x32-10 key.
+ *  Windows narrower than 2 bins, overlaps below 2 bins, 3 > L or L > 256,
+ *  q outside [2, 127] (Potts) are REWL_EINVAL. */
+typedef struct rewl_params {
+    int model;
+    int L;
+    int q;
+    const int8_t *couplings;
+    int64_t e_min;
+    int64_t e_max;
+    int n_windows;
+    double overlap;
+    int walkers_per_window;
+    double flatness;
+    double lnf_init;
+    double lnf_final;
+    int64_t attempts_per_round;
+    uint64_t seed;
+} rewl_params;
+
+typedef struct rewl_ctx rewl_ctx; /* opaque, owned by the library */
+
+/* Device bytes a run needs (device_bytes) and the LDS bytes one walker's
+ * sweep work-group uses (lds_bytes).  REWL_EINVAL if the parameters are
+ * invalid or one walker's window does not fit the 160 KiB LDS of a CU. */
+int rewl_footprint(const rewl_params *p, size_t *device_bytes, size_t *lds_bytes);
+
+/* Create a run: validate, partition the energy range, allocate device state,
+ * then, on the device, draw every walker's random start configuration and walk
+ * it into its window (the start-up step; Ising and Potts walkers that cannot
+ * get there by single-site moves restart from the ordered state).
+ *  device_buffer: NULL to let the library allocate (hipMalloc) and free its
+ *     own memory, or caller-owned device memory of at least rewl_footprint()
+ *     bytes, 256-byte aligned, which the library never frees;
+ *  hip_stream: the hipStream_t all work of this run is queued on (NULL: null
+ *     stream).
+ * On error *out is NULL.  REWL_EINIT if the start-up step fails. */
+int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer,
+                   size_t buffer_bytes, void *hip_stream);
+
+/* Positional form with lnf_init = 1, 10^4 attempts per round, library-owned
+ * memory and the null stream. */
+int rewl_create(rewl_ctx **out, int model, int L, int q, const int8_t *couplings,
+                int64_t e_min, int64_t e_max, int n_windows, double overlap,
+                int walkers_per_window, double flatness, double lnf_final, uint64_t seed);
+
+/* Run rounds until every window is done or max_rounds rounds (< 0: no limit)
+ * have been issued.  A round is: attempts_per_round sweep attempts by every
+ * walker of every unfinished window, the flatness check, the merges, then one
+ * exchange step between windows (k, k+1), k = round mod 2.  Returns REWL_OK
+ * when converged, REWL_NOT_CONVERGED when max_rounds ran out first.
+ * *rounds_done (may be NULL) receives the number of the round in which the
+ * last window finished plus one, or the rounds issued so far. */
+int rewl_run(rewl_ctx *h, int64_t max_rounds, int64_t *rounds_done);
+
+/* Queue exactly `rounds` rounds (no convergence polling, asynchronous). */
+int rewl_step(rewl_ctx *h, int64_t rounds);
+
+/* Stitched, normalised ln g over all n_bins = (e_max - e_min)/e_step + 1
+ * energy bins; bins no walker visited hold -INFINITY.  Normalisation: Ising
+ * ln g(-2N) = ln 2, Potts ln g(-2N) = ln q when the requested range started at
+ * -2N; EA: ln sum g = N ln 2 when it was the whole [-2N, 2N]; otherwise the
+ * lowest visited bin is 0.  cap: entries available in out.  Returns
+ * REWL_NOT_CONVERGED (with the data) when some window is not done yet. */
+int rewl_get_lng(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t *e_min,
+                 int64_t *e_step);
+
+/* Raw state of walker w = window * walkers_per_window + slot: spins (L*L int8,
+ * Potts states 0..q-1), energy, attempts made, flat flag, and the window-local
+ * ln g / H / visited arrays (hi - lo + 1 entries of the walker's window).  Any
+ * output pointer may be NULL. */
+int rewl_get_walker(rewl_ctx *h, int w, int8_t *spins, int64_t *E, uint64_t *t, int *flat,
+                    double *lng, uint32_t *H, uint8_t *visited);
+
+/* Window k: bin range [lo, hi], current ln f, done flag, round it finished in
+ * (-1 before). */
+int rewl_get_window(rewl_ctx *h, int k, int64_t *lo, int64_t *hi, double *lnf, int *done,
+                    int64_t *finish_round);
+
+/* Geometry and counters: bins, energy origin and step, windows, walkers per
+ * window, sites, rounds issued, total sweep attempts made, accepted moves,
+ * exchange proposals and acceptances. */
+int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
+                  int *n_windows, int *walkers_per_window, int *n_sites, int64_t *rounds,
+                  uint64_t *attempts, uint64_t *accepts, uint64_t *ex_prop, uint64_t *ex_acc);
+
+/* Release the run (and its device memory if the library allocated it). */
+void rewl_destroy(rewl_ctx *h);
+
+const char *rewl_last_error(void);
+
+/* Diagnostics: evaluate the device's Philox4x32-10 block for n counters
+ * (ctr: 4n words, key: 2 words, out: 4n words) and the device's ln u for n
+ * word pairs (words: 2n, [2i] = high, [2i+1] = low word; out: n doubles).
+ * Host pointers; synchronous on the null stream. */
+int rewl_selftest_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
+int rewl_selftest_ln_u(const uint32_t *words, double *out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,212 @@
+"""MI355X-native replica-exchange Wang-Landau sampling (arXiv:1305.5615).
+
+Thin Python binding of librewl.so (C ABI in include/rewl.h).  Argument
+marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch supplies the device memory (a uint8 tensor of rewl_footprint() bytes)
+and the stream the kernels are queued on.  There is no CPU fallback: without
+the built library, or without a GPU, creating a run raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "librewl.so")
+
+MODELS = {"ising": 0, "potts": 1, "ea": 2}
+ERRORS = {1: "REWL_NOT_CONVERGED", -1: "REWL_EINVAL", -2: "REWL_ENOMEM", -3: "REWL_EDEVICE",
+          -4: "REWL_EINIT", -5: "REWL_ECORRUPT", -6: "REWL_EBUSY", -7: "REWL_ESTITCH"}
+
+
+class RewlError(RuntimeError):
+    def __init__(self, code, what, detail=""):
+        super().__init__(f"{what}: {ERRORS.get(code, code)} {detail}".strip())
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("model", C.c_int), ("L", C.c_int), ("q", C.c_int),
+                ("couplings", C.c_void_p), ("e_min", C.c_int64), ("e_max", C.c_int64),
+                ("n_windows", C.c_int), ("overlap", C.c_double),
+                ("walkers_per_window", C.c_int), ("flatness", C.c_double),
+                ("lnf_init", C.c_double), ("lnf_final", C.c_double),
+                ("attempts_per_round", C.c_int64), ("seed", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librewl.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with "
+                              "python -m paper_1305_5615_amd.build (hipcc, gfx950)")
+        L = C.CDLL(LIB)
+        P, i64, u64, i32, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_int, C.c_double
+        L.rewl_last_error.restype = C.c_char_p
+        L.rewl_footprint.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t),
+                                     C.POINTER(C.c_size_t)]
+        L.rewl_create_ex.argtypes = [C.POINTER(P), C.POINTER(Params), P, C.c_size_t, P]
+        L.rewl_create.argtypes = [C.POINTER(P), i32, i32, i32, P, i64, i64, i32, dbl, i32, dbl,
+                                  dbl, u64]
+        L.rewl_run.argtypes = [P, i64, C.POINTER(i64)]
+        L.rewl_step.argtypes = [P, i64]
+        L.rewl_get_lng.argtypes = [P, P, i64, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+        L.rewl_get_walker.argtypes = [P, i32, P, P, P, P, P, P, P]
+        L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P]
+        L.rewl_get_info.argtypes = [P] + [P] * 11
+        L.rewl_destroy.argtypes = [P]
+        L.rewl_destroy.restype = None
+        L.rewl_selftest_philox.argtypes = [P, P, P, i32]
+        L.rewl_selftest_ln_u.argtypes = [P, P, i32]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RewlError(rc, what, lib().rewl_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
+                overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
+                lnf_final=1e-6, S=10_000, seed=1):
+    N = L * L
+    if e_min is None:
+        e_min = -2 * N
+    if e_max is None:
+        e_max = 0 if model == "potts" else 2 * N
+    J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
+    p = Params(MODELS[model], L, q, None if J is None else J.ctypes.data, int(e_min),
+               int(e_max), n_windows, overlap, walkers_per_window, flatness, lnf_init,
+               lnf_final, int(S), int(seed))
+    return p, J
+
+
+def footprint(**kw):
+    p, _J = make_params(**kw)
+    dev, lds = C.c_size_t(), C.c_size_t()
+    _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
+    return dev.value, lds.value
+
+
+class Run:
+    """One REWL run on the GPU (see rewl_create_ex)."""
+
+    def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
+                 overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
+                 lnf_final=1e-6, S=10_000, seed=1, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        p, J = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
+                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed)
+        dev, lds = C.c_size_t(), C.c_size_t()
+        _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
+        self._buf = torch.empty(dev.value, dtype=torch.uint8, device="cuda")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().rewl_create_ex(C.byref(h), C.byref(p), C.c_void_p(self._buf.data_ptr()),
+                                    dev.value, C.c_void_p(self._stream.cuda_stream)),
+               "rewl_create_ex")
+        self._h = h
+        self.model, self.L, self.N = model, L, L * L
+        self.params = dict(model=model, L=L, q=q, n_windows=n_windows, overlap=overlap,
+                           walkers_per_window=walkers_per_window, flatness=flatness,
+                           lnf_init=lnf_init, lnf_final=lnf_final, S=S, seed=seed)
+        info = self.info()
+        self.n_bins, self.e_min, self.e_step = info["n_bins"], info["e_min"], info["e_step"]
+        self.h, self.m = info["n_windows"], info["m"]
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().rewl_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        v = [C.c_int64(), C.c_int64(), C.c_int64(), C.c_int(), C.c_int(), C.c_int(),
+             C.c_int64(), C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()]
+        _check(lib().rewl_get_info(self._h, *[C.cast(C.byref(x), C.c_void_p) for x in v]),
+               "rewl_get_info")
+        keys = ["n_bins", "e_min", "e_step", "n_windows", "m", "n_sites", "rounds", "attempts",
+                "accepts", "ex_prop", "ex_acc"]
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def stats(self):
+        i = self.info()
+        return {k: i[k] for k in ("attempts", "accepts", "ex_prop", "ex_acc")}
+
+    def step(self, rounds):
+        _check(lib().rewl_step(self._h, int(rounds)), "rewl_step")
+
+    def run(self, max_rounds=-1):
+        """Rounds to convergence (or max_rounds); returns (converged, rounds)."""
+        r = C.c_int64()
+        rc = _check(lib().rewl_run(self._h, int(max_rounds), C.byref(r)), "rewl_run")
+        return rc == 0, r.value
+
+    def window(self, k):
+        lo, hi, lnf, done, fin = C.c_int64(), C.c_int64(), C.c_double(), C.c_int(), C.c_int64()
+        _check(lib().rewl_get_window(self._h, k, *[C.cast(C.byref(x), C.c_void_p)
+                                                   for x in (lo, hi, lnf, done, fin)]),
+               "rewl_get_window")
+        return {"lo": lo.value, "hi": hi.value, "lnf": lnf.value, "done": bool(done.value),
+                "finish_round": fin.value}
+
+    def windows(self):
+        return [self.window(k) for k in range(self.h)]
+
+    def walker(self, w):
+        win = self.window(w // self.m)
+        W = win["hi"] - win["lo"] + 1
+        spins = np.zeros(self.N, dtype=np.int8)
+        lng = np.zeros(W)
+        H = np.zeros(W, dtype=np.uint32)
+        vis = np.zeros(W, dtype=np.uint8)
+        E, t, flat = C.c_int64(), C.c_uint64(), C.c_int()
+        _check(lib().rewl_get_walker(self._h, w, _p(spins), C.cast(C.byref(E), C.c_void_p),
+                                     C.cast(C.byref(t), C.c_void_p),
+                                     C.cast(C.byref(flat), C.c_void_p), _p(lng), _p(H), _p(vis)),
+               "rewl_get_walker")
+        return {"spins": spins, "E": E.value, "t": t.value, "flat": bool(flat.value),
+                "lng": lng, "H": H, "visited": vis}
+
+    def lng(self):
+        out = np.zeros(self.n_bins)
+        nb, em, es = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().rewl_get_lng(self._h, _p(out), self.n_bins, C.byref(nb), C.byref(em),
+                                  C.byref(es)), "rewl_get_lng")
+        return out
+
+    def energies(self):
+        return self.e_min + self.e_step * np.arange(self.n_bins)
+
+
+def selftest_philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros_like(c)
+    _check(lib().rewl_selftest_philox(_p(c), _p(k), _p(out), c.shape[0]), "selftest_philox")
+    return out
+
+
+def selftest_ln_u(words):
+    w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
+    out = np.zeros(w.shape[0])
+    _check(lib().rewl_selftest_ln_u(_p(w), _p(out), w.shape[0]), "selftest_ln_u")
+    return out

@@ -1,0 +1,100 @@
+// rewl_device.h -- device building blocks of the REWL kernels (gfx950).
+//
+// Compiled with -ffp-contract=off: every floating-point expression below is a
+// sequence of single IEEE binary64 operations rounded to nearest, so results
+// are reproducible on any IEEE machine that evaluates the same operations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rewl {
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications by the round multipliers on counter words 0 and 2,
+// the high halves XOR-ed into the other two words and the round key, the key
+// bumped by the Weyl constants after every round.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// uniform integer in [0, n) from one word
+__device__ __forceinline__ uint32_t mulhi32(uint32_t word, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)word * n) >> 32);
+}
+
+// ln u for u = (2k+1) 2^-53, k = (hi << 20) | (lo >> 12): the odd integer
+// n = 2k+1 < 2^53 is written as f 2^msb with f in [1, 2) directly from its
+// bits, f is folded into [sqrt2/2, sqrt2], and ln f = 2 atanh(s) with
+// s = (f-1)/(f+1) is summed as 2 (s + s z Q(z)), z = s^2,
+// Q(z) = 1/3 + z/5 + ... + z^10/23 (coefficients RN(1/(2i+1))).  ln 2 enters
+// split as LN2_HI (32 fractional bits, so e * LN2_HI is exact) + LN2_LO.
+__device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
+{
+    const double kLn2Hi = 0x1.62e42ffp-1;
+    const double kLn2Lo = -0x1.718432a1b0e26p-35;
+    const double kSqrt2 = 0x1.6a09e667f3bcdp+0;
+    const uint64_t n = ((((uint64_t)hi << 20) | (uint64_t)(lo >> 12)) << 1) | 1u;
+    const int msb = 63 - __clzll((long long)n);
+    const uint64_t mant = (n << (52 - msb)) & 0x000FFFFFFFFFFFFFull;
+    double f = __longlong_as_double((long long)(mant | 0x3FF0000000000000ull));
+    int e = msb - 53;
+    if (f > kSqrt2) {
+        f = f * 0.5;
+        e = e + 1;
+    }
+    const double s = (f - 1.0) / (f + 1.0);
+    const double z = s * s;
+    double Q = 1.0 / 23.0;
+    Q = Q * z + 1.0 / 21.0;
+    Q = Q * z + 1.0 / 19.0;
+    Q = Q * z + 1.0 / 17.0;
+    Q = Q * z + 1.0 / 15.0;
+    Q = Q * z + 1.0 / 13.0;
+    Q = Q * z + 1.0 / 11.0;
+    Q = Q * z + 1.0 / 9.0;
+    Q = Q * z + 1.0 / 7.0;
+    Q = Q * z + 1.0 / 5.0;
+    Q = Q * z + 1.0 / 3.0;
+    const double ed = (double)e;
+    const double lnf = (s + s * (z * Q)) * 2.0;
+    return ed * kLn2Hi + (ed * kLn2Lo + lnf);
+}
+
+// Neighbours of site i = r L + c on the L x L torus.
+struct Nbrs {
+    int rt, lf, dn, up;
+};
+
+__device__ __forceinline__ Nbrs neighbours(int i, int L, int N)
+{
+    const int r = i / L;
+    const int c = i - r * L;
+    Nbrs n;
+    n.rt = (c + 1 == L) ? i - c : i + 1;
+    n.lf = (c == 0) ? i + L - 1 : i - 1;
+    n.dn = (r + 1 == L) ? c : i + L;
+    n.up = (r == 0) ? i + N - L : i - L;
+    return n;
+}
+
+}  // namespace rewl

@@ -1,0 +1,524 @@
+// rewl_kernels.hip -- HIP kernels of replica-exchange Wang-Landau for gfx950.
+//
+// One round of a run is three launches on the run's stream:
+//   sweep_kernel       one work-group (one wave) per walker; the walker's
+//                      spins, ln g and H live in LDS for the whole round;
+//                      the 64 lanes draw 64 attempts at a time (Philox, site,
+//                      neighbours, ln u) in parallel and lane 0 then applies
+//                      them in order, which keeps the sequential single-site
+//                      dynamics of the standard WL walk (standard-WL passage);
+//   flat_merge_kernel  one work-group per window: flatness of each walker,
+//                      and when all m are flat the mean of their ln g, H reset,
+//                      ln f halved (parallel-scheme passage after Eq. (1));
+//   exchange_kernel    one work-group per window pair (k, k+1), k = round mod
+//                      2: partner permutation, Eq. (1) test, configuration swap.
+// The start-up step (random configuration, energy, walk into the window) is
+// init_kernel.  Compiled with -ffp-contract=off (see rewl_device.h).
+#include <hip/hip_runtime.h>
+
+#include "rewl_device.h"
+#include "rewl_internal.h"
+
+using namespace rewl;
+
+namespace {
+
+constexpr int kIsing = 0, kPotts = 1, kEA = 2;
+
+template <int MODEL>
+struct Step {
+    static constexpr int value = (MODEL == kPotts) ? 1 : 4;
+};
+
+// energy change of site `site` going from `old` to `nw`, spins in LDS
+template <int MODEL>
+__device__ __forceinline__ int delta_e(const int8_t *sp, const uint32_t *J4, int site, int rt,
+                                       int lf, int dn, int up, int old, int nw)
+{
+    if (MODEL == kIsing) {
+        return 2 * old * ((int)sp[rt] + (int)sp[lf] + (int)sp[dn] + (int)sp[up]);
+    } else if (MODEL == kEA) {
+        const uint32_t j = J4[site];
+        const int jr = (int8_t)(j & 0xFF), jl = (int8_t)((j >> 8) & 0xFF);
+        const int jd = (int8_t)((j >> 16) & 0xFF), ju = (int8_t)(j >> 24);
+        return 2 * old * (jr * sp[rt] + jl * sp[lf] + jd * sp[dn] + ju * sp[up]);
+    } else {
+        const int so = (sp[rt] == old) + (sp[lf] == old) + (sp[dn] == old) + (sp[up] == old);
+        const int sn = (sp[rt] == nw) + (sp[lf] == nw) + (sp[dn] == nw) + (sp[up] == nw);
+        return so - sn;
+    }
+}
+
+// energy of the bonds to the right and below site i
+template <int MODEL>
+__device__ __forceinline__ int bond_energy(const int8_t *sp, const uint32_t *J4, int i, int L,
+                                           int N)
+{
+    const Nbrs nb = neighbours(i, L, N);
+    if (MODEL == kIsing) return -(sp[i] * sp[nb.rt] + sp[i] * sp[nb.dn]);
+    if (MODEL == kPotts) return -((sp[i] == sp[nb.rt]) + (sp[i] == sp[nb.dn]));
+    const uint32_t j = J4[i];
+    const int jr = (int8_t)(j & 0xFF), jd = (int8_t)((j >> 16) & 0xFF);
+    return -(jr * sp[i] * sp[nb.rt] + jd * sp[i] * sp[nb.dn]);
+}
+
+__device__ __forceinline__ int dist_to(int E, int elo, int ehi)
+{
+    return E < elo ? elo - E : (E > ehi ? E - ehi : 0);
+}
+
+// block-wide integer sum (256 threads)
+__device__ int block_sum_256(int v, int *scratch)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[wave] = v;
+    __syncthreads();
+    int s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += scratch[i];
+    __syncthreads();
+    return s; // valid in thread 0
+}
+
+// ------------------------------------------------------------------ start-up
+// Random configuration from stream 1 (one Philox block per site, word 0),
+// its energy, then single-site moves from stream 2 accepted whenever they do
+// not increase the distance to the window; Ising and Potts walkers still
+// outside after 200 N moves restart from the ordered state, and a walker still
+// outside after 400 N moves (EA: 200 N) fails the start-up.
+template <int MODEL>
+__global__ __launch_bounds__(256) void init_kernel(RunDev a)
+{
+    const int w = blockIdx.x, k = w / a.m, N = a.N, L = a.L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Prop *stage = reinterpret_cast<Prop *>(smem);
+    int *scratch = reinterpret_cast<int *>(stage + kBlock);   // 8 ints
+    uint32_t *J_s = reinterpret_cast<uint32_t *>(scratch + 8);
+    int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
+    __shared__ int sh_E, sh_stop, sh_used;
+
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const U4 r = philox((uint32_t)i, 0u, (uint32_t)w, 1u, a.key0, a.key1);
+        sp[i] = (MODEL == kPotts) ? (int8_t)mulhi32(r.x, (uint32_t)a.q) : ((r.x >> 31) ? 1 : -1);
+        if (MODEL == kEA) J_s[i] = a.J4[i];
+    }
+    __syncthreads();
+    int e = 0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) e += bond_energy<MODEL>(sp, J_s, i, L, N);
+    e = block_sum_256(e, scratch);
+    const int elo = a.e_min + a.lo[k] * a.step, ehi = a.e_min + a.hi[k] * a.step;
+    if (threadIdx.x == 0) {
+        sh_E = e;
+        sh_stop = dist_to(e, elo, ehi) == 0;
+    }
+    __syncthreads();
+    const unsigned long long cap = 200ull * (unsigned long long)N;
+    unsigned long long d = 0;
+    while (!sh_stop) {
+        if (threadIdx.x < kBlock) {
+            const unsigned long long c = d + threadIdx.x;
+            const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 2u, a.key0, a.key1);
+            const int site = (int)mulhi32(r.x, (uint32_t)N);
+            const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(a.q - 1)) : 0u;
+            const Nbrs nb = neighbours(site, L, N);
+            Prop p;
+            p.thr = 0.0;
+            p.site_r1 = (uint32_t)site | (r1 << 16);
+            p.nb_rl = (uint32_t)nb.rt | ((uint32_t)nb.lf << 16);
+            p.nb_du = (uint32_t)nb.dn | ((uint32_t)nb.up << 16);
+            stage[threadIdx.x] = p;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int E = sh_E, stop = 0, j = 0;
+            for (; j < kBlock; ++j) {
+                if (dist_to(E, elo, ehi) == 0) { stop = 1; break; }
+                const unsigned long long dd = d + j;
+                if (dd == cap) {
+                    if (MODEL == kEA) { a.status[0] = 1; stop = 1; break; }
+                    const int8_t v = (MODEL == kPotts) ? 0 : 1;
+                    for (int i = 0; i < N; ++i) sp[i] = v;
+                    E = -2 * N;
+                }
+                if (dd == 2 * cap) { a.status[0] = 1; stop = 1; break; }
+                const Prop p = stage[j];
+                const int site = (int)(p.site_r1 & 0xFFFFu);
+                const int old = sp[site];
+                int nw;
+                if (MODEL == kPotts) {
+                    nw = old + (int)(p.site_r1 >> 16);
+                    if (nw >= a.q) nw -= a.q;
+                } else {
+                    nw = -old;
+                }
+                const int En = E + delta_e<MODEL>(sp, J_s, site, (int)(p.nb_rl & 0xFFFFu),
+                                                  (int)(p.nb_rl >> 16), (int)(p.nb_du & 0xFFFFu),
+                                                  (int)(p.nb_du >> 16), old, nw);
+                if (dist_to(En, elo, ehi) <= dist_to(E, elo, ehi)) {
+                    sp[site] = (int8_t)nw;
+                    E = En;
+                }
+            }
+            if (!stop && dist_to(E, elo, ehi) == 0) stop = 1;
+            sh_E = E;
+            sh_stop = stop;
+            sh_used = j;
+        }
+        __syncthreads();
+        d += (unsigned long long)sh_used;
+    }
+    int8_t *sg = a.spins + (size_t)w * a.Npad;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sg[i] = sp[i];
+    if (threadIdx.x == 0) a.E[w] = sh_E;
+}
+
+// ------------------------------------------------------------------- sweep
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
+{
+    const int w = blockIdx.x, k = w / a.m;
+    if (a.done[k]) return;
+    const int lane = threadIdx.x, N = a.N, L = a.L;
+    constexpr int STEP = Step<MODEL>::value;
+    const int lo = a.lo[k], W = a.hi[k] - lo + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *lng_s = reinterpret_cast<double *>(smem);
+    Prop *stage = reinterpret_cast<Prop *>(lng_s + W);
+    uint32_t *H_s = reinterpret_cast<uint32_t *>(stage + kBlock);
+    uint32_t *J_s = H_s + ((W + 1) & ~1);
+    int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
+
+    double *lng_g = a.lng + (size_t)w * a.Wmax;
+    uint32_t *H_g = a.H + (size_t)w * a.Wmax;
+    int8_t *sp_g = a.spins + (size_t)w * a.Npad;
+    for (int i = lane; i < W; i += kBlock) {
+        lng_s[i] = lng_g[i];
+        H_s[i] = H_g[i];
+    }
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
+        for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
+    }
+    if (MODEL == kEA)
+        for (int i = lane; i < N; i += kBlock) J_s[i] = a.J4[i];
+    __syncthreads();
+
+    const int elo = a.e_min + lo * STEP, ehi = elo + (W - 1) * STEP;
+    const double lnf = a.lnf[k];
+    const unsigned long long t0 = a.t[w];
+    const long long S = a.S;
+    int E = a.E[w];
+    int b = (E - elo) / STEP;
+    double gcur = lng_s[b];
+    unsigned int acc = 0;
+
+    for (long long base = 0; base < S; base += kBlock) {
+        const int n = (S - base < kBlock) ? (int)(S - base) : kBlock;
+        if (lane < n) {
+            const unsigned long long c = t0 + (unsigned long long)base + lane;
+            const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
+            const int site = (int)mulhi32(r.x, (uint32_t)N);
+            const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(a.q - 1)) : 0u;
+            const Nbrs nb = neighbours(site, L, N);
+            Prop p;
+            p.thr = ln_u(r.z, r.w);
+            p.site_r1 = (uint32_t)site | (r1 << 16);
+            p.nb_rl = (uint32_t)nb.rt | ((uint32_t)nb.lf << 16);
+            p.nb_du = (uint32_t)nb.dn | ((uint32_t)nb.up << 16);
+            stage[lane] = p;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            for (int j = 0; j < n; ++j) {
+                const Prop p = stage[j];
+                const int site = (int)(p.site_r1 & 0xFFFFu);
+                const int old = sp[site];
+                int nw;
+                if (MODEL == kPotts) {
+                    nw = old + (int)(p.site_r1 >> 16);
+                    if (nw >= a.q) nw -= a.q;
+                } else {
+                    nw = -old;
+                }
+                const int En = E + delta_e<MODEL>(sp, J_s, site, (int)(p.nb_rl & 0xFFFFu),
+                                                  (int)(p.nb_rl >> 16), (int)(p.nb_du & 0xFFFFu),
+                                                  (int)(p.nb_du >> 16), old, nw);
+                if (En >= elo && En <= ehi) {
+                    const int bn = (En - elo) / STEP;
+                    const double gn = lng_s[bn];
+                    if (gcur - gn > p.thr) {
+                        sp[site] = (int8_t)nw;
+                        E = En;
+                        b = bn;
+                        gcur = gn;
+                        ++acc;
+                    }
+                }
+                gcur = gcur + lnf;
+                lng_s[b] = gcur;
+                H_s[b] += 1u;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int i = lane; i < W; i += kBlock) {
+        lng_g[i] = lng_s[i];
+        H_g[i] = H_s[i];
+    }
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
+        for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
+    }
+    if (lane == 0) {
+        a.E[w] = E;
+        a.t[w] = t0 + (unsigned long long)S;
+        a.n_acc[w] += acc;
+    }
+}
+
+// ------------------------------------------------------- flatness + merge
+// flat <=> min H * n >= p * sum H over the walker's visited bins (lng > 0);
+// when all m walkers of the window are flat: ln g <- (sum_s ln g_s) / m summed
+// s = 0..m-1 in order, H <- 0, flags cleared, ln f halved, done below lnf_final.
+__global__ __launch_bounds__(256) void flat_merge_kernel(RunDev a, long long round)
+{
+    const int k = blockIdx.x;
+    if (a.done[k]) return;
+    const int lo = a.lo[k], W = a.hi[k] - lo + 1, m = a.m;
+    __shared__ unsigned long long sh_sum[4];
+    __shared__ unsigned int sh_min[4], sh_n[4];
+    __shared__ int sh_all;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int s = 0; s < m; ++s) {
+        const int w = k * m + s;
+        if (a.flat[w]) continue;
+        const double *g = a.lng + (size_t)w * a.Wmax;
+        const uint32_t *H = a.H + (size_t)w * a.Wmax;
+        unsigned long long sum = 0;
+        unsigned int hmin = 0xFFFFFFFFu, n = 0;
+        for (int i = tid; i < W; i += blockDim.x) {
+            if (g[i] > 0.0) {
+                const uint32_t h = H[i];
+                sum += h;
+                n += 1;
+                hmin = h < hmin ? h : hmin;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sum += __shfl_xor(sum, off);
+            n += __shfl_xor(n, off);
+            const unsigned int o = __shfl_xor(hmin, off);
+            hmin = o < hmin ? o : hmin;
+        }
+        if ((tid & 63) == 0) {
+            sh_sum[wave] = sum;
+            sh_min[wave] = hmin;
+            sh_n[wave] = n;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+                sum += sh_sum[i];
+                n += sh_n[i];
+                hmin = sh_min[i] < hmin ? sh_min[i] : hmin;
+            }
+            const int f = (n > 0) && ((double)hmin * (double)n >= a.flat_p * (double)sum);
+            a.flat[w] = f;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int all = 1;
+        for (int s = 0; s < m; ++s) all &= (a.flat[k * m + s] != 0);
+        sh_all = all;
+    }
+    __syncthreads();
+    if (!sh_all) return;
+    const bool pow2 = (m & (m - 1)) == 0;
+    const double inv = 1.0 / (double)m;
+    for (int i = tid; i < W; i += blockDim.x) {
+        double sum = 0.0;
+        for (int s = 0; s < m; ++s) sum = sum + a.lng[(size_t)(k * m + s) * a.Wmax + i];
+        const double mean = pow2 ? sum * inv : sum / (double)m;
+        for (int s = 0; s < m; ++s) {
+            a.lng[(size_t)(k * m + s) * a.Wmax + i] = mean;
+            a.H[(size_t)(k * m + s) * a.Wmax + i] = 0u;
+        }
+    }
+    if (tid == 0) {
+        for (int s = 0; s < m; ++s) a.flat[k * m + s] = 0;
+        const double nl = a.lnf[k] * 0.5;
+        a.lnf[k] = nl;
+        if (nl < a.lnf_final) {
+            a.done[k] = 1;
+            a.finish[k] = round;
+        }
+    }
+}
+
+// -------------------------------------------------------------- exchange
+// Stream-3 words of pair (k, k+1) in round r come from counters
+// (r_lo, r_hi, k, 3 | call << 8): first m-1 words for a Fisher-Yates shuffle
+// pi of the slots of window k+1 (a = m-1 .. 1 swaps pi[a], pi[mulhi(word, a+1)]),
+// then two words per slot a for u.  Walker a of window k (configuration X)
+// and walker pi[a] of window k+1 (configuration Y) swap configurations iff
+// both energies lie in both windows and
+// ln u < [ln g_i(E_X) - ln g_i(E_Y)] + [ln g_j(E_Y) - ln g_j(E_X)]   (Eq. (1)).
+__global__ __launch_bounds__(256) void exchange_kernel(RunDev a, long long round)
+{
+    const int k = 2 * (int)blockIdx.x + (int)(round & 1);
+    if (k + 1 >= a.h) return;
+    if (a.done[k] || a.done[k + 1]) return;
+    const int m = a.m;
+    __shared__ int sh_n, sh_wi[64], sh_wj[64], perm[64];
+    if (threadIdx.x == 0) {
+        uint32_t buf[4] = {0, 0, 0, 0};
+        uint32_t call = 0;
+        int idx = 4;
+        auto next = [&]() -> uint32_t {
+            if (idx == 4) {
+                const U4 r = philox((uint32_t)round, (uint32_t)((unsigned long long)round >> 32),
+                                    (uint32_t)k, 3u | (call << 8), a.key0, a.key1);
+                buf[0] = r.x; buf[1] = r.y; buf[2] = r.z; buf[3] = r.w;
+                call += 1;
+                idx = 0;
+            }
+            return buf[idx++];
+        };
+        for (int s = 0; s < m; ++s) perm[s] = s;
+        for (int s = m - 1; s >= 1; --s) {
+            const int j = (int)mulhi32(next(), (uint32_t)(s + 1));
+            const int x = perm[s];
+            perm[s] = perm[j];
+            perm[j] = x;
+        }
+        const int lo_i = a.lo[k], hi_i = a.hi[k], lo_j = a.lo[k + 1], hi_j = a.hi[k + 1];
+        int n = 0;
+        unsigned long long acc = 0;
+        for (int s = 0; s < m; ++s) {
+            const uint32_t hi = next();
+            const uint32_t lo = next();
+            const double thr = ln_u(hi, lo);
+            const int wi = k * m + s, wj = (k + 1) * m + perm[s];
+            const int EX = a.E[wi], EY = a.E[wj];
+            const int bX = (EX - a.e_min) / a.step, bY = (EY - a.e_min) / a.step;
+            if (bX < lo_j || bX > hi_j || bY < lo_i || bY > hi_i) continue;
+            const double *gi = a.lng + (size_t)wi * a.Wmax;
+            const double *gj = a.lng + (size_t)wj * a.Wmax;
+            const double lnP = (gi[bX - lo_i] - gi[bY - lo_i]) + (gj[bY - lo_j] - gj[bX - lo_j]);
+            if (thr < lnP) {
+                a.E[wi] = EY;
+                a.E[wj] = EX;
+                sh_wi[n] = wi;
+                sh_wj[n] = wj;
+                ++n;
+                ++acc;
+            }
+        }
+        a.ex_prop[k] += (unsigned long long)m;
+        a.ex_acc[k] += acc;
+        sh_n = n;
+    }
+    __syncthreads();
+    const int words = a.Npad / 4;
+    for (int p = 0; p < sh_n; ++p) {
+        uint32_t *x = reinterpret_cast<uint32_t *>(a.spins + (size_t)sh_wi[p] * a.Npad);
+        uint32_t *y = reinterpret_cast<uint32_t *>(a.spins + (size_t)sh_wj[p] * a.Npad);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) {
+            const uint32_t v = x[i];
+            x[i] = y[i];
+            y[i] = v;
+        }
+    }
+}
+
+__global__ void selftest_philox_kernel(const uint32_t *ctr, uint32_t k0, uint32_t k1,
+                                       uint32_t *out, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+    out[4 * i] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+__global__ void selftest_ln_u_kernel(const uint32_t *words, double *out, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = ln_u(words[2 * i], words[2 * i + 1]);
+}
+
+template <int MODEL>
+int launch_init_t(const RunDev &a, hipStream_t s)
+{
+    const size_t lds = kBlock * sizeof(Prop) + 8 * sizeof(int) +
+                       (MODEL == kEA ? (size_t)a.N * 4 : 0) + (size_t)a.N + 16;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -3;
+    hipLaunchKernelGGL(init_kernel<MODEL>, dim3(a.nw), dim3(256), lds, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int MODEL>
+int launch_round_t(const RunDev &a, long long round, hipStream_t s, size_t lds)
+{
+    static size_t lds_set = 64 * 1024;
+    if (lds > lds_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<MODEL>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kMaxLds) != hipSuccess)
+            return -3;
+        lds_set = kMaxLds;
+    }
+    hipLaunchKernelGGL(sweep_kernel<MODEL>, dim3(a.nw), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(flat_merge_kernel, dim3(a.h), dim3(256), 0, s, a, round);
+    hipLaunchKernelGGL(exchange_kernel, dim3((a.h + 1) / 2), dim3(256), 0, s, a, round);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace
+
+int rewl_launch_init(const RunDev &a, void *stream)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch (a.model) {
+    case kIsing: return launch_init_t<kIsing>(a, s);
+    case kPotts: return launch_init_t<kPotts>(a, s);
+    default: return launch_init_t<kEA>(a, s);
+    }
+}
+
+int rewl_launch_round(const RunDev &a, long long round, void *stream)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t lds = sweep_lds_bytes(a.model, a.Wmax, a.N);
+    switch (a.model) {
+    case kIsing: return launch_round_t<kIsing>(a, round, s, lds);
+    case kPotts: return launch_round_t<kPotts>(a, round, s, lds);
+    default: return launch_round_t<kEA>(a, round, s, lds);
+    }
+}
+
+int rewl_launch_selftest_philox(const uint32_t *ctr_d, uint32_t k0, uint32_t k1, uint32_t *out_d,
+                                int n)
+{
+    hipLaunchKernelGGL(selftest_philox_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, ctr_d, k0,
+                       k1, out_d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int rewl_launch_selftest_ln_u(const uint32_t *words_d, double *out_d, int n)
+{
+    hipLaunchKernelGGL(selftest_ln_u_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, words_d,
+                       out_d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}

@@ -1,0 +1,154 @@
+"""GPU path against the CPU oracle, element by element (needs an MI355X).
+
+The GPU library and the oracle share no code; they are fed the same seeded
+parameters (and the same +-J couplings from workloads.py) and must agree
+bit for bit on every walker's spins, energy, attempt counter, flat flag, ln g,
+H and visited set, on every window's ln f / done flag / finishing round, and
+on the counters, after a fixed number of rounds.  The stitched ln g of a
+converged run must agree too.
+"""
+import numpy as np
+import pytest
+
+from workloads import ea_couplings, run_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_1305_5615_amd as rewl
+
+    rewl.lib()
+    return rewl
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_lib):
+    return oracle_lib
+
+
+def _kw(p):
+    keys = ("model", "L", "q", "couplings", "e_min", "e_max", "n_windows", "overlap",
+            "walkers_per_window", "flatness", "lnf_init", "lnf_final", "S", "seed")
+    return {k: p[k] for k in keys if k in p}
+
+
+def _pair(gpu, orc, **kw):
+    print("case:", {k: v for k, v in kw.items() if k != "couplings"}, flush=True)
+    return gpu.Run(**kw), orc.Run(**kw)
+
+
+def assert_same_state(g, o, label=""):
+    assert g.n_bins == o.n_bins and g.e_min == o.e_min and g.e_step == o.e_step
+    for k in range(o.h):
+        wg, wo = g.window(k), o.window(k)
+        assert wg == wo, (label, "window", k, wg, wo)
+    for w in range(o.h * o.m):
+        a, b = g.walker(w), o.walker(w)
+        for key in ("E", "t", "flat"):
+            assert a[key] == b[key], (label, "walker", w, key, a[key], b[key])
+        for key in ("spins", "H", "visited"):
+            assert np.array_equal(a[key], b[key]), (label, "walker", w, key)
+        # ln g bit for bit
+        assert np.array_equal(a["lng"].view(np.uint64), b["lng"].view(np.uint64)), \
+            (label, "walker", w, "lng", np.abs(a["lng"] - b["lng"]).max())
+    sg, so = g.stats(), o.stats()
+    assert sg == so, (label, sg, so)
+
+
+def test_philox_bitexact(gpu, orc):
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0x12345678, 0x9ABCDEF0], dtype=np.uint32)
+    out = gpu.selftest_philox(ctr, key)
+    for i in range(0, 4096, 37):
+        assert np.array_equal(out[i], orc.philox(ctr[i], key))
+
+
+def test_ln_u_bitexact(gpu, orc):
+    rng = np.random.default_rng(2)
+    words = rng.integers(0, 2 ** 32, size=(20000, 2), dtype=np.uint64).astype(np.uint32)
+    words[:4] = [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0x80000000, 0], [0xB504F333, 0xF9DE6000]]
+    got = gpu.selftest_ln_u(words)
+    ref = np.array([orc.ln_u(orc.uniform(int(h), int(lo))) for h, lo in words])
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+CASES = [
+    # name, parameters (small sizes that still span several 64-attempt blocks,
+    # a ragged last block, merges and finished windows)
+    ("ising8", dict(model="ising", L=8, n_windows=4, walkers_per_window=2, S=1000,
+                    lnf_final=1e-2, seed=3)),
+    ("potts12q5", dict(model="potts", L=12, q=5, n_windows=5, walkers_per_window=2, S=777,
+                       lnf_final=1e-2, seed=4)),
+    ("ea10", dict(model="ea", L=10, n_windows=4, walkers_per_window=4, S=1000, lnf_final=1e-2,
+                  seed=5)),
+    ("ising5_odd", dict(model="ising", L=5, n_windows=3, walkers_per_window=3, S=65,
+                        lnf_final=1e-2, seed=6)),
+    ("potts6q2_m1", dict(model="potts", L=6, q=2, n_windows=2, walkers_per_window=1, S=1,
+                         lnf_final=0.3, seed=7)),
+    ("ising12_range", dict(model="ising", L=12, n_windows=3, walkers_per_window=2, S=500,
+                           e_min=-240, e_max=40, lnf_final=1e-2, seed=8)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_rounds_bitexact(gpu, orc, name, kw):
+    kw = dict(kw)
+    if kw["model"] == "ea":
+        kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+    g, o = _pair(gpu, orc, **kw)
+    assert_same_state(g, o, "start-up")
+    done_rounds = 0
+    for rounds in (1, 2, 7, 40, 150):
+        g.step(rounds)
+        o.step(rounds)
+        done_rounds += rounds
+        assert_same_state(g, o, f"{name} after {done_rounds} rounds")
+
+
+def test_ising8_full_run_bitexact(gpu, orc):
+    """The small Ising workload run to convergence: same rounds, same stitched ln g."""
+    p = run_params("ising8", seed=2)
+    g, o = _pair(gpu, orc, **_kw(p))
+    ok_g, rounds_g = g.run()
+    ok_o = o.run()
+    assert ok_g and ok_o
+    assert rounds_g == max(w["finish_round"] for w in o.windows()) + 1
+    assert_same_state(g, o, "converged")
+    lg, lo = g.lng(), o.lng()
+    assert np.array_equal(np.isfinite(lg), np.isfinite(lo))
+    fin = np.isfinite(lo)
+    assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
+
+
+@pytest.mark.parametrize("name,rounds", [("ising32", 3), ("potts64", 1), ("ea24", 2)])
+def test_full_size_rounds_bitexact(gpu, orc, name, rounds):
+    """The full-size workloads (32x32 Ising 16x4, 64x64 q=10 Potts 32x8, 24x24
+    +-J 8x4) for a few rounds of 10^4 attempts per walker, in the launch
+    configuration the benchmark times."""
+    p = run_params(name, seed=1)
+    kw = _kw(p)
+    print("case:", name, flush=True)
+    g = gpu.Run(**kw)
+    o = orc.Run(**kw, n_threads=0)
+    assert_same_state(g, o, f"{name} start-up")
+    g.step(rounds)
+    o.step(rounds)
+    assert_same_state(g, o, f"{name} after {rounds} rounds")
+
+
+def test_invalid_arguments_rejected(gpu):
+    with pytest.raises(gpu.RewlError) as e:
+        gpu.Run("ising", 2)
+    assert e.value.code == -1
+    with pytest.raises(gpu.RewlError):
+        gpu.Run("potts", 8, q=1)
+    with pytest.raises(gpu.RewlError):
+        gpu.Run("ising", 8, n_windows=64)
+    with pytest.raises(gpu.RewlError):
+        gpu.Run("ising", 8, walkers_per_window=65)

@@ -449,7 +449,7 @@ def test_invalid_arguments(oracle_lib):
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.Run("ising", 8, overlap=1.0)
     with pytest.raises(oracle_lib.OracleError):
-        oracle_lib.Run("ising", 8, n_windows=40)   # windows narrower than 2 bins
+        oracle_lib.Run("ising", 8, n_windows=64)   # windows narrower than 2 bins
 
 
 # ----------------------------------------------------- convergence to truth --
