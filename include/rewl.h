@@ -149,6 +149,14 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
                   int *n_windows, int *walkers_per_window, int *n_sites, int64_t *rounds,
                   uint64_t *attempts, uint64_t *accepts, uint64_t *ex_prop, uint64_t *ex_acc);
 
+/* Timing of the sweep kernel: with on != 0, every later round records a HIP
+ * event right before and right after its sweep launch on the run's stream;
+ * rewl_get_timing synchronises the stream and returns the summed elapsed time
+ * of those launches (milliseconds) and their number since the last
+ * rewl_set_timing.  Costs two event records per round; off by default. */
+int rewl_set_timing(rewl_ctx *h, int on);
+int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches);
+
 /* Release the run (and its device memory if the library allocated it). */
 void rewl_destroy(rewl_ctx *h);
 

@@ -62,6 +62,8 @@ def lib():
         L.rewl_get_info.argtypes = [P] + [P] * 11
         L.rewl_destroy.argtypes = [P]
         L.rewl_destroy.restype = None
+        L.rewl_set_timing.argtypes = [P, i32]
+        L.rewl_get_timing.argtypes = [P, C.POINTER(dbl), C.POINTER(i64)]
         L.rewl_selftest_philox.argtypes = [P, P, P, i32]
         L.rewl_selftest_ln_u.argtypes = [P, P, i32]
         _lib = L
@@ -195,6 +197,15 @@ class Run:
 
     def energies(self):
         return self.e_min + self.e_step * np.arange(self.n_bins)
+
+    def set_timing(self, on=True):
+        _check(lib().rewl_set_timing(self._h, 1 if on else 0), "rewl_set_timing")
+
+    def timing(self):
+        """(summed sweep-kernel milliseconds, sweep launches) since set_timing."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().rewl_get_timing(self._h, C.byref(ms), C.byref(n)), "rewl_get_timing")
+        return ms.value, n.value
 
 
 def selftest_philox(ctr, key):

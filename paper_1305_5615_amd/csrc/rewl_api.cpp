@@ -181,13 +181,46 @@ struct rewl_ctx {
     RunDev dev{};
     int64_t rounds = 0;
     int *pinned = nullptr; // done flags, polled by rewl_run
+    // optional timing of the sweep launches with events on the run's stream
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free, ev_pending; // pending: start/stop pairs
+    double sweep_ms = 0.0;
+    int64_t sweep_launches = 0;
 };
 
 namespace {
 
+// Fold finished start/stop event pairs into the sweep time (stream synced).
+int collect_timing(rewl_ctx *h)
+{
+    for (size_t i = 0; i + 1 < h->ev_pending.size(); i += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev_pending[i], h->ev_pending[i + 1]));
+        h->sweep_ms += ms;
+        h->sweep_launches += 1;
+        h->ev_free.push_back(h->ev_pending[i]);
+        h->ev_free.push_back(h->ev_pending[i + 1]);
+    }
+    h->ev_pending.clear();
+    return REWL_OK;
+}
+
 int sync(rewl_ctx *h)
 {
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return h->timing ? collect_timing(h) : REWL_OK;
+}
+
+int take_event(rewl_ctx *h, hipEvent_t *e)
+{
+    if (h->ev_free.empty()) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        h->ev_free.push_back(ev);
+    }
+    *e = h->ev_free.back();
+    h->ev_free.pop_back();
+    h->ev_pending.push_back(*e);
     return REWL_OK;
 }
 
@@ -305,6 +338,8 @@ void rewl_destroy(rewl_ctx *h)
     if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
     if (h->owns && h->base) (void)hipFree(h->base);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->ev_pending) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -357,6 +392,7 @@ int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer, si
     d.Wmax = g.Wmax;
     d.e_min = (int)g.e_min;
     d.step = g.step;
+    d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
     d.S = p->attempts_per_round;
     d.key0 = (uint32_t)p->seed;
     d.key1 = (uint32_t)(p->seed >> 32);
@@ -446,10 +482,37 @@ int rewl_step(rewl_ctx *h, int64_t rounds)
 {
     if (!h || rounds < 0) return fail(REWL_EINVAL, "bad handle or negative rounds");
     for (int64_t i = 0; i < rounds; ++i) {
-        int rc = rewl_launch_round(h->dev, h->rounds, h->stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->timing) {
+            int rc = take_event(h, &e0);
+            if (!rc) rc = take_event(h, &e1);
+            if (rc) return rc;
+        }
+        int rc = rewl_launch_round(h->dev, h->rounds, h->stream, e0, e1);
         if (rc) return fail(rc, "kernel launch failed");
         h->rounds += 1;
     }
+    return REWL_OK;
+}
+
+int rewl_set_timing(rewl_ctx *h, int on)
+{
+    if (!h) return fail(REWL_EINVAL, "bad handle");
+    int rc = sync(h);
+    if (rc) return rc;
+    h->timing = on != 0;
+    h->sweep_ms = 0.0;
+    h->sweep_launches = 0;
+    return REWL_OK;
+}
+
+int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches)
+{
+    if (!h) return fail(REWL_EINVAL, "bad handle");
+    int rc = sync(h);
+    if (rc) return rc;
+    if (sweep_ms) *sweep_ms = h->sweep_ms;
+    if (sweep_launches) *sweep_launches = h->sweep_launches;
     return REWL_OK;
 }
 

@@ -80,14 +80,15 @@ __device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
     return ed * kLn2Hi + (ed * kLn2Lo + lnf);
 }
 
-// Neighbours of site i = r L + c on the L x L torus.
+// Neighbours of site i = r L + c on the L x L torus; the row is
+// mulhi(i, ceil(2^32 / L)), exact for i < 2^16 and L <= 256.
 struct Nbrs {
     int rt, lf, dn, up;
 };
 
-__device__ __forceinline__ Nbrs neighbours(int i, int L, int N)
+__device__ __forceinline__ Nbrs neighbours(int i, int L, int N, uint32_t l_magic)
 {
-    const int r = i / L;
+    const int r = (int)__umulhi((uint32_t)i, l_magic);
     const int c = i - r * L;
     Nbrs n;
     n.rt = (c + 1 == L) ? i - c : i + 1;

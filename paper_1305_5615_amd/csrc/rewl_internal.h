@@ -22,6 +22,7 @@ struct RunDev {
     int model, L, N, q, h, m, nw;
     int Npad, Wmax;
     int e_min, step;
+    uint32_t l_magic;  // ceil(2^32 / L): row = mulhi(site, l_magic) for site < L*L
     long long S;
     uint32_t key0, key1;
     double flat_p, lnf_final;
@@ -41,26 +42,38 @@ struct RunDev {
     int *status;
 };
 
-// Proposals staged per block of the sweep (one per lane), 24 bytes each.
+// Proposals staged per block of the sweep (one per lane), decoded so that
+// the in-order pass over them needs no unpacking.
 constexpr int kBlock = 64;
-struct alignas(8) Prop {
+struct alignas(16) Prop {
     double thr;        // ln u of the attempt
-    uint32_t site_r1;  // site | (Potts state offset r1 << 16)
-    uint32_t nb_rl;    // right | left << 16
-    uint32_t nb_du;    // down | up << 16
+    int32_t d_off;     // energy change against the block-start configuration
+    int32_t d_addr;    // the same change in bytes of the per-bin LDS records
+    uint32_t sp_off;   // LDS byte offset of the site's spin
+    uint32_t flags;    // new state (8 bits) | old state << 8 | Potts r1 << 16
+                       // | 1 << 31 if an earlier proposal of the block touches
+                       //   the site or one of its neighbours
+    uint32_t site;
     uint32_t pad;
 };
 
-// LDS bytes of one walker's sweep work-group: ln g (8 W), staged proposals,
-// H (4 W), EA couplings (4 N), spins (N).
+// Per-bin LDS record of the sweep: ln g and H side by side.
+struct alignas(16) BinRec {
+    double lng;
+    uint32_t H;
+    uint32_t pad;
+};
+
+// LDS bytes of one walker's sweep work-group: bins (16 W), staged proposals,
+// per-site proposal masks (8 N), EA couplings (4 N), spins (N).
 inline size_t sweep_lds_bytes(int model, int W, int N)
 {
     size_t b = 0;
-    b += (size_t)W * 8;
-    b += (size_t)kBlock * sizeof(Prop);
-    b += ((size_t)W * 4 + 7) & ~(size_t)7;
+    b += (size_t)W * sizeof(BinRec);
+    b += (size_t)(kBlock + 1) * sizeof(Prop);
+    b += (size_t)N * 8;
     if (model == 2) b += (size_t)N * 4;
-    b += ((size_t)N + 7) & ~(size_t)7;
+    b += ((size_t)N + 15) & ~(size_t)15;
     return b;
 }
 
@@ -68,7 +81,8 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 // launchers (rewl_kernels.hip)
 int rewl_launch_init(const RunDev &a, void *stream);
-int rewl_launch_round(const RunDev &a, long long round, void *stream);
+// ev0/ev1 (hipEvent_t or NULL) are recorded right before and after the sweep
+int rewl_launch_round(const RunDev &a, long long round, void *stream, void *ev0, void *ev1);
 int rewl_launch_selftest_philox(const uint32_t *ctr_d, uint32_t k0, uint32_t k1, uint32_t *out_d,
                                 int n);
 int rewl_launch_selftest_ln_u(const uint32_t *words_d, double *out_d, int n);

@@ -52,15 +52,20 @@ __device__ __forceinline__ int delta_e(const int8_t *sp, const uint32_t *J4, int
 // energy of the bonds to the right and below site i
 template <int MODEL>
 __device__ __forceinline__ int bond_energy(const int8_t *sp, const uint32_t *J4, int i, int L,
-                                           int N)
+                                           int N, uint32_t l_magic)
 {
-    const Nbrs nb = neighbours(i, L, N);
+    const Nbrs nb = neighbours(i, L, N, l_magic);
     if (MODEL == kIsing) return -(sp[i] * sp[nb.rt] + sp[i] * sp[nb.dn]);
     if (MODEL == kPotts) return -((sp[i] == sp[nb.rt]) + (sp[i] == sp[nb.dn]));
     const uint32_t j = J4[i];
     const int jr = (int8_t)(j & 0xFF), jd = (int8_t)((j >> 16) & 0xFF);
     return -(jr * sp[i] * sp[nb.rt] + jd * sp[i] * sp[nb.dn]);
 }
+
+// a start-up move: site, Potts offset and the four neighbours
+struct Move {
+    uint32_t site_r1, nb_rl, nb_du, pad;
+};
 
 __device__ __forceinline__ int dist_to(int E, int elo, int ehi)
 {
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
 {
     const int w = blockIdx.x, k = w / a.m, N = a.N, L = a.L;
     extern __shared__ __align__(16) unsigned char smem[];
-    Prop *stage = reinterpret_cast<Prop *>(smem);
+    Move *stage = reinterpret_cast<Move *>(smem);
     int *scratch = reinterpret_cast<int *>(stage + kBlock);   // 8 ints
     uint32_t *J_s = reinterpret_cast<uint32_t *>(scratch + 8);
     int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
     }
     __syncthreads();
     int e = 0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) e += bond_energy<MODEL>(sp, J_s, i, L, N);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) e += bond_energy<MODEL>(sp, J_s, i, L, N, a.l_magic);
     e = block_sum_256(e, scratch);
     const int elo = a.e_min + a.lo[k] * a.step, ehi = a.e_min + a.hi[k] * a.step;
     if (threadIdx.x == 0) {
@@ -121,9 +126,8 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
             const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 2u, a.key0, a.key1);
             const int site = (int)mulhi32(r.x, (uint32_t)N);
             const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(a.q - 1)) : 0u;
-            const Nbrs nb = neighbours(site, L, N);
-            Prop p;
-            p.thr = 0.0;
+            const Nbrs nb = neighbours(site, L, N, a.l_magic);
+            Move p;
             p.site_r1 = (uint32_t)site | (r1 << 16);
             p.nb_rl = (uint32_t)nb.rt | ((uint32_t)nb.lf << 16);
             p.nb_du = (uint32_t)nb.dn | ((uint32_t)nb.up << 16);
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
                     E = -2 * N;
                 }
                 if (dd == 2 * cap) { a.status[0] = 1; stop = 1; break; }
-                const Prop p = stage[j];
+                const Move p = stage[j];
                 const int site = (int)(p.site_r1 & 0xFFFFu);
                 const int old = sp[site];
                 int nw;
@@ -174,99 +178,173 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
 }
 
 // ------------------------------------------------------------------- sweep
+// Attempts are taken 64 at a time.  Lane i draws attempt t+i (Philox stream
+// 0: site, Potts offset, u -> ln u), computes its energy change against the
+// configuration at the start of the block, and flags it when an earlier
+// proposal of the block hits its site or a neighbour (per-site 64-bit masks in
+// LDS).  Lane 0 then applies the 64 attempts in order; a flagged attempt
+// recomputes its energy change from the current spins, every other one uses
+// the precomputed value, so the result is that of the plain sequential walk.
+template <int MODEL>
+__device__ __forceinline__ int new_state(int old, uint32_t r1, int q)
+{
+    if (MODEL == kPotts) {
+        int nw = old + (int)r1;
+        return nw >= q ? nw - q : nw;
+    }
+    return -old;
+}
+
 template <int MODEL>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
 {
     const int w = blockIdx.x, k = w / a.m;
     if (a.done[k]) return;
-    const int lane = threadIdx.x, N = a.N, L = a.L;
+    const int lane = threadIdx.x, N = a.N, L = a.L, q = a.q;
     constexpr int STEP = Step<MODEL>::value;
+    constexpr int ADDR_PER_E = (int)sizeof(BinRec) / STEP;
     const int lo = a.lo[k], W = a.hi[k] - lo + 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    double *lng_s = reinterpret_cast<double *>(smem);
-    Prop *stage = reinterpret_cast<Prop *>(lng_s + W);
-    uint32_t *H_s = reinterpret_cast<uint32_t *>(stage + kBlock);
-    uint32_t *J_s = H_s + ((W + 1) & ~1);
+    BinRec *bins = reinterpret_cast<BinRec *>(smem);
+    Prop *stage = reinterpret_cast<Prop *>(bins + W);
+    uint64_t *tag = reinterpret_cast<uint64_t *>(stage + kBlock + 1);
+    uint32_t *J_s = reinterpret_cast<uint32_t *>(tag + N);
     int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
+    const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - smem);
 
     double *lng_g = a.lng + (size_t)w * a.Wmax;
     uint32_t *H_g = a.H + (size_t)w * a.Wmax;
     int8_t *sp_g = a.spins + (size_t)w * a.Npad;
     for (int i = lane; i < W; i += kBlock) {
-        lng_s[i] = lng_g[i];
-        H_s[i] = H_g[i];
+        bins[i].lng = lng_g[i];
+        bins[i].H = H_g[i];
     }
     {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
         for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
     }
+    for (int i = lane; i < N; i += kBlock) tag[i] = 0ull;
     if (MODEL == kEA)
         for (int i = lane; i < N; i += kBlock) J_s[i] = a.J4[i];
     __syncthreads();
 
-    const int elo = a.e_min + lo * STEP, ehi = elo + (W - 1) * STEP;
+    const int elo = a.e_min + lo * STEP;
+    const unsigned span = (unsigned)((W - 1) * STEP);
     const double lnf = a.lnf[k];
     const unsigned long long t0 = a.t[w];
     const long long S = a.S;
-    int E = a.E[w];
-    int b = (E - elo) / STEP;
-    double gcur = lng_s[b];
+    // chain state: energy offset from the window's lowest energy, LDS byte
+    // offset of the current bin's record, its ln g
+    int eoff = a.E[w] - elo;
+    uint32_t baddr = (uint32_t)(eoff / STEP) * (uint32_t)sizeof(BinRec);
+    double gcur = bins[eoff / STEP].lng;
     unsigned int acc = 0;
+    const uint64_t bit = 1ull << lane;
 
     for (long long base = 0; base < S; base += kBlock) {
         const int n = (S - base < kBlock) ? (int)(S - base) : kBlock;
-        if (lane < n) {
+        const bool active = lane < n;
+        int site = 0;
+        if (active) {
             const unsigned long long c = t0 + (unsigned long long)base + lane;
             const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
-            const int site = (int)mulhi32(r.x, (uint32_t)N);
-            const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(a.q - 1)) : 0u;
-            const Nbrs nb = neighbours(site, L, N);
+            site = (int)mulhi32(r.x, (uint32_t)N);
+            const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(q - 1)) : 0u;
+            const Nbrs nb = neighbours(site, L, N, a.l_magic);
+            const int old = sp[site];
+            const int nw = new_state<MODEL>(old, r1, q);
+            const int dE = delta_e<MODEL>(sp, J_s, site, nb.rt, nb.lf, nb.dn, nb.up, old, nw);
+            atomicOr(reinterpret_cast<unsigned long long *>(&tag[site]), (unsigned long long)bit);
+            const uint64_t seen = tag[site] | tag[nb.rt] | tag[nb.lf] | tag[nb.dn] | tag[nb.up];
             Prop p;
             p.thr = ln_u(r.z, r.w);
-            p.site_r1 = (uint32_t)site | (r1 << 16);
-            p.nb_rl = (uint32_t)nb.rt | ((uint32_t)nb.lf << 16);
-            p.nb_du = (uint32_t)nb.dn | ((uint32_t)nb.up << 16);
+            p.d_off = dE;
+            p.d_addr = dE * ADDR_PER_E;
+            p.sp_off = sp_base + (uint32_t)site;
+            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (r1 << 16) |
+                      ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
+            p.site = (uint32_t)site;
+            p.pad = 0;
             stage[lane] = p;
         }
         __syncthreads();
+        if (active) tag[site] = 0ull;
         if (lane == 0) {
-            for (int j = 0; j < n; ++j) {
-                const Prop p = stage[j];
-                const int site = (int)(p.site_r1 & 0xFFFFu);
-                const int old = sp[site];
-                int nw;
-                if (MODEL == kPotts) {
-                    nw = old + (int)(p.site_r1 >> 16);
-                    if (nw >= a.q) nw -= a.q;
-                } else {
-                    nw = -old;
+            // In-order pass, branch-free except for flagged attempts: the
+            // candidate bin is clamped into the window so its ln g can always
+            // be loaded, H grows with an LDS atomic, and full blocks run
+            // unrolled so the staged records load ahead of use.
+            // fields the fast path needs, loaded one attempt ahead; the site
+            // of a flagged attempt is read from LDS only on that slow path
+            struct Fast {
+                double thr;
+                int d_off, d_addr;
+                uint32_t sp_off, flags;
+            };
+            auto fetch = [&](int j) {
+                Fast f;
+                f.thr = stage[j].thr;
+                f.d_off = stage[j].d_off;
+                f.d_addr = stage[j].d_addr;
+                f.sp_off = stage[j].sp_off;
+                f.flags = stage[j].flags;
+                return f;
+            };
+            auto attempt = [&](const Fast &p, int j) {
+                int d_off = p.d_off, d_addr = p.d_addr;
+                int nw = (int)(int8_t)(p.flags & 0xFFu);
+                int old = (int)(int8_t)((p.flags >> 8) & 0xFFu);
+                if (p.flags & 0x80000000u) {
+                    const int s = (int)stage[j].site;
+                    const Nbrs nb = neighbours(s, L, N, a.l_magic);
+                    old = sp[s];
+                    nw = new_state<MODEL>(old, (p.flags >> 16) & 0x7Fu, q);
+                    d_off = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, old, nw);
+                    d_addr = d_off * ADDR_PER_E;
                 }
-                const int En = E + delta_e<MODEL>(sp, J_s, site, (int)(p.nb_rl & 0xFFFFu),
-                                                  (int)(p.nb_rl >> 16), (int)(p.nb_du & 0xFFFFu),
-                                                  (int)(p.nb_du >> 16), old, nw);
-                if (En >= elo && En <= ehi) {
-                    const int bn = (En - elo) / STEP;
-                    const double gn = lng_s[bn];
-                    if (gcur - gn > p.thr) {
-                        sp[site] = (int8_t)nw;
-                        E = En;
-                        b = bn;
-                        gcur = gn;
-                        ++acc;
-                    }
-                }
+                const int off = eoff + d_off;
+                const bool inwin = (unsigned)off <= span;
+                const uint32_t naddr = inwin ? baddr + (uint32_t)d_addr : baddr;
+                const double gn = *reinterpret_cast<const double *>(smem + naddr);
+                const bool accept = inwin & (gcur - gn > p.thr);
+                smem[p.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
+                eoff = accept ? off : eoff;
+                baddr = accept ? naddr : baddr;
+                gcur = accept ? gn : gcur;
+                acc += accept ? 1u : 0u;
                 gcur = gcur + lnf;
-                lng_s[b] = gcur;
-                H_s[b] += 1u;
+                *reinterpret_cast<double *>(smem + baddr) = gcur;
+                atomicAdd(reinterpret_cast<uint32_t *>(smem + baddr + 8), 1u);
+            };
+            // each record is loaded before the previous attempt's LDS stores,
+            // which the compiler may not move loads across
+            Fast cur = fetch(0);
+            if (n == kBlock) {
+#pragma unroll
+                for (int j = 0; j < kBlock; ++j) {
+                    const Fast nxt = fetch(j + 1);
+                    // keep the use of the next record out of this attempt, so
+                    // its load latency hides behind this attempt's ln g load
+                    __builtin_amdgcn_sched_barrier(0);
+                    attempt(cur, j);
+                    __builtin_amdgcn_sched_barrier(0);
+                    cur = nxt;
+                }
+            } else {
+                for (int j = 0; j < n; ++j) {
+                    const Fast nxt = fetch(j + 1);
+                    attempt(cur, j);
+                    cur = nxt;
+                }
             }
         }
         __syncthreads();
     }
 
     for (int i = lane; i < W; i += kBlock) {
-        lng_g[i] = lng_s[i];
-        H_g[i] = H_s[i];
+        lng_g[i] = bins[i].lng;
+        H_g[i] = bins[i].H;
     }
     {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
@@ -274,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
         for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
     }
     if (lane == 0) {
-        a.E[w] = E;
+        a.E[w] = eoff + elo;
         a.t[w] = t0 + (unsigned long long)S;
         a.n_acc[w] += acc;
     }
@@ -458,7 +536,7 @@ __global__ void selftest_ln_u_kernel(const uint32_t *words, double *out, int n)
 template <int MODEL>
 int launch_init_t(const RunDev &a, hipStream_t s)
 {
-    const size_t lds = kBlock * sizeof(Prop) + 8 * sizeof(int) +
+    const size_t lds = kBlock * sizeof(Move) + 8 * sizeof(int) +
                        (MODEL == kEA ? (size_t)a.N * 4 : 0) + (size_t)a.N + 16;
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
@@ -469,7 +547,8 @@ int launch_init_t(const RunDev &a, hipStream_t s)
 }
 
 template <int MODEL>
-int launch_round_t(const RunDev &a, long long round, hipStream_t s, size_t lds)
+int launch_round_t(const RunDev &a, long long round, hipStream_t s, size_t lds, hipEvent_t e0,
+                   hipEvent_t e1)
 {
     static size_t lds_set = 64 * 1024;
     if (lds > lds_set) {
@@ -479,7 +558,9 @@ int launch_round_t(const RunDev &a, long long round, hipStream_t s, size_t lds)
             return -3;
         lds_set = kMaxLds;
     }
+    if (e0 && hipEventRecord(e0, s) != hipSuccess) return -3;
     hipLaunchKernelGGL(sweep_kernel<MODEL>, dim3(a.nw), dim3(kBlock), lds, s, a);
+    if (e1 && hipEventRecord(e1, s) != hipSuccess) return -3;
     hipLaunchKernelGGL(flat_merge_kernel, dim3(a.h), dim3(256), 0, s, a, round);
     hipLaunchKernelGGL(exchange_kernel, dim3((a.h + 1) / 2), dim3(256), 0, s, a, round);
     return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -497,14 +578,15 @@ int rewl_launch_init(const RunDev &a, void *stream)
     }
 }
 
-int rewl_launch_round(const RunDev &a, long long round, void *stream)
+int rewl_launch_round(const RunDev &a, long long round, void *stream, void *ev0, void *ev1)
 {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0 = reinterpret_cast<hipEvent_t>(ev0), e1 = reinterpret_cast<hipEvent_t>(ev1);
     const size_t lds = sweep_lds_bytes(a.model, a.Wmax, a.N);
     switch (a.model) {
-    case kIsing: return launch_round_t<kIsing>(a, round, s, lds);
-    case kPotts: return launch_round_t<kPotts>(a, round, s, lds);
-    default: return launch_round_t<kEA>(a, round, s, lds);
+    case kIsing: return launch_round_t<kIsing>(a, round, s, lds, e0, e1);
+    case kPotts: return launch_round_t<kPotts>(a, round, s, lds, e0, e1);
+    default: return launch_round_t<kEA>(a, round, s, lds, e0, e1);
     }
 }
 
