@@ -109,14 +109,18 @@ def cpu_baseline(p, seconds):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="ising32", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--max-rounds", type=int, default=200000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rounds", type=int, default=0,
                     help="profile mode: one run, this many rounds after start-up, then exit")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="profile mode: this many runs of the workload (seeds 1..n) in one batch")
+    ap.add_argument("--walkers-per-wave", type=int, default=1)
+    ap.add_argument("--graph", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: each REWL run lives on one device and "
@@ -133,6 +137,25 @@ def main():
     base = dict(run_params(args.workload, seed=1))
     model = base["model"]
 
+    if args.rounds > 0 and args.batch > 0:
+        runs = [run_kwargs(run_params(args.workload, seed=1 + i)) for i in range(args.batch)]
+        b = rewl.Batch(runs, walkers_per_wave=args.walkers_per_wave, graph_rounds=args.graph)
+        if not args.graph:
+            b.set_timing(True)
+        b.step(1)
+        torch.cuda.synchronize()
+        a0 = sum(b[i].info()["attempts"] for i in range(len(b)))
+        t0 = time.perf_counter()
+        b.step(args.rounds)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, n = b.timing()
+        att = sum(b[i].info()["attempts"] for i in range(len(b))) - a0
+        log(f"profile: {args.batch} x {args.workload}, P={args.walkers_per_wave}, "
+            f"graph={args.graph}, {args.rounds} rounds, {att} attempts, {dt:.3f} s, "
+            f"{att / dt / 1e9:.3f} G attempts/s, sweep avg {1e3 * ms / max(n, 1):.1f} us")
+        b.close()
+        return
     if args.rounds > 0:
         r = rewl.Run(**run_kwargs(base))
         r.set_timing(True)

@@ -157,8 +157,66 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
 int rewl_set_timing(rewl_ctx *h, int on);
 int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches);
 
-/* Release the run (and its device memory if the library allocated it). */
+/* Release a run made by rewl_create_ex / rewl_create (and its device memory if
+ * the library allocated it).  Runs obtained from a batch are released with the
+ * batch; rewl_destroy ignores them. */
 void rewl_destroy(rewl_ctx *h);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent runs advanced together: every round is one launch of each
+ * kernel over all runs (sweep groups of walkers_per_wave walkers of one run per
+ * wave, windows, window pairs) plus a round-counter update, on one stream.
+ * Each run keeps its own round counter, seed and state, so its results are
+ * bit-identical to the same run made alone with rewl_create_ex.  Run i's state
+ * is read with the rewl_get_* functions on the handle rewl_batch_get_run
+ * returns (owned by the batch).
+ *  walkers_per_wave: 1, 2, 4 or 8 (0: 1); more walkers per wave share each
+ *    wave's instructions, fewer give each walker a whole wave (lower latency).
+ *  REWL_EINVAL if the walkers of one wave do not fit the LDS of a CU. */
+typedef struct rewl_batch rewl_batch;
+int rewl_batch_create(rewl_batch **out, const rewl_params *runs, int n_runs,
+                      int walkers_per_wave, void *hip_stream);
+int rewl_batch_get_run(rewl_batch *b, int i, rewl_ctx **run);
+int rewl_batch_set_walkers_per_wave(rewl_batch *b, int walkers_per_wave);
+/* rounds_per_graph > 0: rounds are issued as replays of a captured HIP graph of
+ * that many rounds (remaining rounds as direct launches); 0: direct launches.
+ * Graphs are not used while timing is on. */
+int rewl_batch_set_graph(rewl_batch *b, int rounds_per_graph);
+int rewl_batch_step(rewl_batch *b, int64_t rounds);
+/* Rounds until every run is done or max_rounds (< 0: no limit) issued;
+ * *rounds_issued: rounds issued by the batch so far.  REWL_NOT_CONVERGED if
+ * some run is still running. */
+int rewl_batch_run(rewl_batch *b, int64_t max_rounds, int64_t *rounds_issued);
+/* flags[i] = 1 when run i is done (cap >= number of runs). */
+int rewl_batch_done(rewl_batch *b, int *flags, int cap);
+int rewl_batch_set_timing(rewl_batch *b, int on);
+int rewl_batch_get_timing(rewl_batch *b, double *sweep_ms, int64_t *sweep_launches);
+void rewl_batch_destroy(rewl_batch *b);
+
+/* ------------------------------------------------------------------ server
+ * Continuous batching of arriving runs.  Submitted runs wait in arrival order
+ * and are admitted at round boundaries while their device state fits the
+ * budget (and, lowering walkers_per_wave if needed, their LDS footprint fits a
+ * CU); admitted runs start their own round count at 0 and are advanced together
+ * with the runs already on the device; a finished run is stitched on the host,
+ * its device state freed, and its result kept until released.  A run's result
+ * is bit-identical to the same run made alone.
+ *  rewl_server_tick: retire finished runs, admit waiting ones, then advance all
+ *    running runs by rounds_per_tick rounds (synchronous in its retire step).
+ *  rewl_server_next_done: id of the next finished run (REWL_NOT_CONVERGED when
+ *    none) and the rounds it ran.
+ *  rewl_server_result: its stitched, normalised ln g (as rewl_get_lng).
+ *  REWL_EBUSY from submit: the run alone exceeds the device budget. */
+typedef struct rewl_server rewl_server;
+int rewl_server_create(rewl_server **out, size_t device_budget_bytes, int walkers_per_wave,
+                       int rounds_per_tick, void *hip_stream);
+int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id);
+int rewl_server_tick(rewl_server *s, int *n_running, int *n_queued);
+int rewl_server_next_done(rewl_server *s, int64_t *id, int64_t *rounds);
+int rewl_server_result(rewl_server *s, int64_t id, double *out, int64_t cap, int64_t *n_bins,
+                       int64_t *e_min, int64_t *e_step);
+int rewl_server_release(rewl_server *s, int64_t id);
+void rewl_server_destroy(rewl_server *s);
 
 const char *rewl_last_error(void);
 

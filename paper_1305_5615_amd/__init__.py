@@ -64,6 +64,26 @@ def lib():
         L.rewl_destroy.restype = None
         L.rewl_set_timing.argtypes = [P, i32]
         L.rewl_get_timing.argtypes = [P, C.POINTER(dbl), C.POINTER(i64)]
+        L.rewl_batch_create.argtypes = [C.POINTER(P), P, i32, i32, P]
+        L.rewl_batch_get_run.argtypes = [P, i32, C.POINTER(P)]
+        L.rewl_batch_set_walkers_per_wave.argtypes = [P, i32]
+        L.rewl_batch_set_graph.argtypes = [P, i32]
+        L.rewl_batch_step.argtypes = [P, i64]
+        L.rewl_batch_run.argtypes = [P, i64, C.POINTER(i64)]
+        L.rewl_batch_done.argtypes = [P, P, i32]
+        L.rewl_batch_set_timing.argtypes = [P, i32]
+        L.rewl_batch_get_timing.argtypes = [P, C.POINTER(dbl), C.POINTER(i64)]
+        L.rewl_batch_destroy.argtypes = [P]
+        L.rewl_batch_destroy.restype = None
+        L.rewl_server_create.argtypes = [C.POINTER(P), C.c_size_t, i32, i32, P]
+        L.rewl_server_submit.argtypes = [P, C.POINTER(Params), C.POINTER(i64)]
+        L.rewl_server_tick.argtypes = [P, C.POINTER(i32), C.POINTER(i32)]
+        L.rewl_server_next_done.argtypes = [P, C.POINTER(i64), C.POINTER(i64)]
+        L.rewl_server_result.argtypes = [P, i64, P, i64, C.POINTER(i64), C.POINTER(i64),
+                                         C.POINTER(i64)]
+        L.rewl_server_release.argtypes = [P, i64]
+        L.rewl_server_destroy.argtypes = [P]
+        L.rewl_server_destroy.restype = None
         L.rewl_selftest_philox.argtypes = [P, P, P, i32]
         L.rewl_selftest_ln_u.argtypes = [P, P, i32]
         _lib = L
@@ -102,43 +122,16 @@ def footprint(**kw):
     return dev.value, lds.value
 
 
-class Run:
-    """One REWL run on the GPU (see rewl_create_ex)."""
+class RunView:
+    """Readers of one run's state (a run made alone, or run i of a batch)."""
 
-    def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
-                 overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                 lnf_final=1e-6, S=10_000, seed=1, stream=None):
-        import torch
-
-        if not torch.cuda.is_available():
-            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
-        p, J = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
-                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed)
-        dev, lds = C.c_size_t(), C.c_size_t()
-        _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
-        self._buf = torch.empty(dev.value, dtype=torch.uint8, device="cuda")
-        self._stream = stream if stream is not None else torch.cuda.current_stream()
-        h = C.c_void_p()
-        _check(lib().rewl_create_ex(C.byref(h), C.byref(p), C.c_void_p(self._buf.data_ptr()),
-                                    dev.value, C.c_void_p(self._stream.cuda_stream)),
-               "rewl_create_ex")
+    def _attach(self, h, model, L, params):
         self._h = h
         self.model, self.L, self.N = model, L, L * L
-        self.params = dict(model=model, L=L, q=q, n_windows=n_windows, overlap=overlap,
-                           walkers_per_window=walkers_per_window, flatness=flatness,
-                           lnf_init=lnf_init, lnf_final=lnf_final, S=S, seed=seed)
+        self.params = params
         info = self.info()
         self.n_bins, self.e_min, self.e_step = info["n_bins"], info["e_min"], info["e_step"]
         self.h, self.m = info["n_windows"], info["m"]
-
-    def close(self):
-        h = getattr(self, "_h", None)
-        if h:
-            lib().rewl_destroy(h)
-            self._h = None
-
-    def __del__(self):
-        self.close()
 
     def info(self):
         v = [C.c_int64(), C.c_int64(), C.c_int64(), C.c_int(), C.c_int(), C.c_int(),
@@ -152,15 +145,6 @@ class Run:
     def stats(self):
         i = self.info()
         return {k: i[k] for k in ("attempts", "accepts", "ex_prop", "ex_acc")}
-
-    def step(self, rounds):
-        _check(lib().rewl_step(self._h, int(rounds)), "rewl_step")
-
-    def run(self, max_rounds=-1):
-        """Rounds to convergence (or max_rounds); returns (converged, rounds)."""
-        r = C.c_int64()
-        rc = _check(lib().rewl_run(self._h, int(max_rounds), C.byref(r)), "rewl_run")
-        return rc == 0, r.value
 
     def window(self, k):
         lo, hi, lnf, done, fin = C.c_int64(), C.c_int64(), C.c_double(), C.c_int(), C.c_int64()
@@ -198,6 +182,50 @@ class Run:
     def energies(self):
         return self.e_min + self.e_step * np.arange(self.n_bins)
 
+
+class Run(RunView):
+    """One REWL run on the GPU (see rewl_create_ex)."""
+
+    def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
+                 overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
+                 lnf_final=1e-6, S=10_000, seed=1, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        p, J = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
+                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed)
+        dev, lds = C.c_size_t(), C.c_size_t()
+        _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
+        self._buf = torch.empty(dev.value, dtype=torch.uint8, device="cuda")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().rewl_create_ex(C.byref(h), C.byref(p), C.c_void_p(self._buf.data_ptr()),
+                                    dev.value, C.c_void_p(self._stream.cuda_stream)),
+               "rewl_create_ex")
+        self._attach(h, model, L, dict(model=model, L=L, q=q, n_windows=n_windows,
+                                       overlap=overlap, walkers_per_window=walkers_per_window,
+                                       flatness=flatness, lnf_init=lnf_init,
+                                       lnf_final=lnf_final, S=S, seed=seed))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().rewl_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, rounds):
+        _check(lib().rewl_step(self._h, int(rounds)), "rewl_step")
+
+    def run(self, max_rounds=-1):
+        """Rounds to convergence (or max_rounds); returns (converged, rounds)."""
+        r = C.c_int64()
+        rc = _check(lib().rewl_run(self._h, int(max_rounds), C.byref(r)), "rewl_run")
+        return rc == 0, r.value
+
     def set_timing(self, on=True):
         _check(lib().rewl_set_timing(self._h, 1 if on else 0), "rewl_set_timing")
 
@@ -206,6 +234,141 @@ class Run:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().rewl_get_timing(self._h, C.byref(ms), C.byref(n)), "rewl_get_timing")
         return ms.value, n.value
+
+
+class Batch:
+    """Many independent runs advanced together (see rewl_batch_create).
+
+    runs: list of keyword dicts as for Run (model, L, q, couplings, ...).
+    """
+
+    def __init__(self, runs, walkers_per_wave=1, graph_rounds=0, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        self._keep = []
+        arr = (Params * len(runs))()
+        for i, kw in enumerate(runs):
+            p, J = make_params(**kw)
+            self._keep.append(J)
+            arr[i] = p
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().rewl_batch_create(C.byref(h), C.cast(arr, C.c_void_p), len(runs),
+                                       int(walkers_per_wave), C.c_void_p(self._stream.cuda_stream)),
+               "rewl_batch_create")
+        self._h = h
+        self.n = len(runs)
+        self._views = []
+        for i, kw in enumerate(runs):
+            rh = C.c_void_p()
+            _check(lib().rewl_batch_get_run(self._h, i, C.byref(rh)), "rewl_batch_get_run")
+            v = RunView()
+            v._attach(rh, kw["model"], kw["L"], dict(kw))
+            self._views.append(v)
+        if graph_rounds:
+            self.set_graph(graph_rounds)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().rewl_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __getitem__(self, i):
+        return self._views[i]
+
+    def __len__(self):
+        return self.n
+
+    def set_walkers_per_wave(self, P):
+        _check(lib().rewl_batch_set_walkers_per_wave(self._h, int(P)), "set_walkers_per_wave")
+
+    def set_graph(self, rounds):
+        _check(lib().rewl_batch_set_graph(self._h, int(rounds)), "rewl_batch_set_graph")
+
+    def step(self, rounds):
+        _check(lib().rewl_batch_step(self._h, int(rounds)), "rewl_batch_step")
+
+    def run(self, max_rounds=-1):
+        r = C.c_int64()
+        rc = _check(lib().rewl_batch_run(self._h, int(max_rounds), C.byref(r)), "rewl_batch_run")
+        return rc == 0, r.value
+
+    def done(self):
+        f = np.zeros(self.n, dtype=np.int32)
+        _check(lib().rewl_batch_done(self._h, _p(f), self.n), "rewl_batch_done")
+        return f.astype(bool)
+
+    def set_timing(self, on=True):
+        _check(lib().rewl_batch_set_timing(self._h, 1 if on else 0), "rewl_batch_set_timing")
+
+    def timing(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().rewl_batch_get_timing(self._h, C.byref(ms), C.byref(n)), "timing")
+        return ms.value, n.value
+
+
+class Server:
+    """Continuous batching of arriving runs (see rewl_server_create)."""
+
+    def __init__(self, device_budget_bytes=8 << 30, walkers_per_wave=1, rounds_per_tick=8,
+                 stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().rewl_server_create(C.byref(h), int(device_budget_bytes),
+                                        int(walkers_per_wave), int(rounds_per_tick),
+                                        C.c_void_p(self._stream.cuda_stream)),
+               "rewl_server_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().rewl_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, **kw):
+        p, J = make_params(**kw)
+        rid = C.c_int64()
+        _check(lib().rewl_server_submit(self._h, C.byref(p), C.byref(rid)), "rewl_server_submit")
+        return rid.value
+
+    def tick(self):
+        """Retire finished runs, admit waiting ones, advance; returns (running, queued)."""
+        r, q = C.c_int(), C.c_int()
+        _check(lib().rewl_server_tick(self._h, C.byref(r), C.byref(q)), "rewl_server_tick")
+        return r.value, q.value
+
+    def next_done(self):
+        """(id, rounds) of the next finished run, or None."""
+        rid, rounds = C.c_int64(), C.c_int64()
+        rc = _check(lib().rewl_server_next_done(self._h, C.byref(rid), C.byref(rounds)),
+                    "rewl_server_next_done")
+        return None if rc == 1 else (rid.value, rounds.value)
+
+    def result(self, rid):
+        nb, em, es = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().rewl_server_result(self._h, int(rid), None, 0, C.byref(nb), C.byref(em),
+                                        C.byref(es)), "rewl_server_result")
+        out = np.zeros(nb.value)
+        _check(lib().rewl_server_result(self._h, int(rid), _p(out), nb.value, C.byref(nb),
+                                        C.byref(em), C.byref(es)), "rewl_server_result")
+        return out
+
+    def release(self, rid):
+        _check(lib().rewl_server_release(self._h, int(rid)), "rewl_server_release")
 
 
 def selftest_philox(ctr, key):

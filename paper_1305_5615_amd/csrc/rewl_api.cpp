@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -127,7 +128,7 @@ int validate(const rewl_params *p, Geometry &g)
         g.Wmax = std::max<int>(g.Wmax, (int)(g.hi[k] - g.lo[k] + 1));
     g.nw = p->n_windows * p->walkers_per_window;
     g.Npad = (int)align_up((size_t)N, 16);
-    if (sweep_lds_bytes(p->model, g.Wmax, g.N) > kMaxLds)
+    if (sweep_lds_bytes(1, g.Wmax, g.N, p->model == REWL_EA) > kMaxLds)
         return fail(REWL_EINVAL, "one walker's window does not fit the LDS of a CU");
     return REWL_OK;
 }
@@ -135,7 +136,7 @@ int validate(const rewl_params *p, Geometry &g)
 // Byte offsets of the arrays inside the device allocation.
 struct Layout {
     size_t spins, E, t, flat, lng, H, n_acc, lnf, done, finish, lo, hi, ex_prop, ex_acc, J4,
-        status, total;
+        round, status, total;
 };
 
 Layout layout(const rewl_params *p, const Geometry &g)
@@ -163,6 +164,7 @@ Layout layout(const rewl_params *p, const Geometry &g)
     l.ex_prop = take(h * 8);
     l.ex_acc = take(h * 8);
     l.J4 = take(p->model == REWL_EA ? (size_t)g.N * 4 : 4);
+    l.round = take(8);
     l.status = take(4);
     l.total = off;
     return l;
@@ -170,6 +172,10 @@ Layout layout(const rewl_params *p, const Geometry &g)
 
 }  // namespace
 
+struct rewl_batch;
+
+// One run: its parameters, geometry and device slab.  A run is stepped by the
+// batch it belongs to; a run made by rewl_create_ex owns a private batch.
 struct rewl_ctx {
     rewl_params p{};
     std::vector<int8_t> couplings;
@@ -177,50 +183,69 @@ struct rewl_ctx {
     Layout l{};
     void *base = nullptr;
     bool owns = false;
+    RunDesc desc{};
+    rewl_batch *batch = nullptr;
+    bool own_batch = false;
+    int64_t id = -1;          // server request id
+    int64_t admit_round = 0;  // server: batch round at admission
+};
+
+// A set of runs advanced together, round by round, by one stream.
+struct rewl_batch {
+    std::vector<rewl_ctx *> runs;  // slot i; nullptr = free slot (server)
+    bool owns_runs = false;
     hipStream_t stream = nullptr;
-    RunDev dev{};
+    int P = 1;                     // walkers per wave in the sweep
+    void *tab = nullptr;           // device work tables + per-run done flags
+    size_t tab_cap = 0;
+    BatchDev dev{};
+    int *done_d = nullptr;
+    bool dirty = true;
     int64_t rounds = 0;
-    int *pinned = nullptr; // done flags, polled by rewl_run
-    // optional timing of the sweep launches with events on the run's stream
+    int *pinned = nullptr;
+    size_t pinned_cap = 0;
     bool timing = false;
-    std::vector<hipEvent_t> ev_free, ev_pending; // pending: start/stop pairs
+    std::vector<hipEvent_t> ev_free, ev_pending;
     double sweep_ms = 0.0;
     int64_t sweep_launches = 0;
+    int graph_rounds = 0;          // > 0: replay a captured graph of this many rounds
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
+    hipStream_t cap_stream = nullptr; // private stream the graph is captured on
 };
 
 namespace {
 
-// Fold finished start/stop event pairs into the sweep time (stream synced).
-int collect_timing(rewl_ctx *h)
+int collect_timing(rewl_batch *b)
 {
-    for (size_t i = 0; i + 1 < h->ev_pending.size(); i += 2) {
+    for (size_t i = 0; i + 1 < b->ev_pending.size(); i += 2) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->ev_pending[i], h->ev_pending[i + 1]));
-        h->sweep_ms += ms;
-        h->sweep_launches += 1;
-        h->ev_free.push_back(h->ev_pending[i]);
-        h->ev_free.push_back(h->ev_pending[i + 1]);
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev_pending[i], b->ev_pending[i + 1]));
+        b->sweep_ms += ms;
+        b->sweep_launches += 1;
+        b->ev_free.push_back(b->ev_pending[i]);
+        b->ev_free.push_back(b->ev_pending[i + 1]);
     }
-    h->ev_pending.clear();
+    b->ev_pending.clear();
     return REWL_OK;
 }
 
-int sync(rewl_ctx *h)
+int bsync(rewl_batch *b)
 {
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return h->timing ? collect_timing(h) : REWL_OK;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return b->timing ? collect_timing(b) : REWL_OK;
 }
 
-int take_event(rewl_ctx *h, hipEvent_t *e)
+int take_event(rewl_batch *b, hipEvent_t *e)
 {
-    if (h->ev_free.empty()) {
+    if (b->ev_free.empty()) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev));
-        h->ev_free.push_back(ev);
+        b->ev_free.push_back(ev);
     }
-    *e = h->ev_free.back();
-    h->ev_free.pop_back();
-    h->ev_pending.push_back(*e);
+    *e = b->ev_free.back();
+    b->ev_free.pop_back();
+    b->ev_pending.push_back(*e);
     return REWL_OK;
 }
 
@@ -228,9 +253,335 @@ template <class T>
 int d2h(rewl_ctx *h, T *dst, size_t off, size_t count)
 {
     HIP_TRY(hipMemcpyAsync(dst, (char *)h->base + off, count * sizeof(T), hipMemcpyDeviceToHost,
-                           h->stream));
-    return sync(h);
+                           h->batch->stream));
+    return bsync(h->batch);
 }
+
+void drop_graph(rewl_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_src) (void)hipGraphDestroy(b->graph_src);
+    b->graph = nullptr;
+    b->graph_src = nullptr;
+}
+
+// Work lists of the live runs: sweep groups of P walkers, windows, pair slots.
+int rebuild(rewl_batch *b)
+{
+    drop_graph(b);
+    std::vector<RunDesc> descs;
+    std::vector<SweepItem> sweep;
+    std::vector<WinItem> win, pair;
+    int max_N = 1, max_W = 1, any_ea = 0;
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+        rewl_ctx *r = b->runs[i];
+        if (!r) continue;
+        const int idx = (int)descs.size();
+        descs.push_back(r->desc);
+        for (int w = 0; w < r->g.nw; w += b->P)
+            sweep.push_back(SweepItem{idx, w, std::min(b->P, r->g.nw - w), 0});
+        for (int k = 0; k < r->p.n_windows; ++k) win.push_back(WinItem{idx, k});
+        for (int k = 0; k < r->p.n_windows / 2; ++k) pair.push_back(WinItem{idx, k});
+        max_N = std::max(max_N, r->g.N);
+        max_W = std::max(max_W, r->g.Wmax);
+        any_ea |= r->p.model == REWL_EA;
+    }
+    if (sweep_lds_bytes(b->P, max_W, max_N, any_ea != 0) > kMaxLds)
+        return fail(REWL_EINVAL, "walkers_per_wave too large for these runs' LDS footprint");
+    const size_t n_runs = descs.size();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t o_runs = take(n_runs * sizeof(RunDesc)), o_sw = take(sweep.size() * sizeof(SweepItem));
+    const size_t o_win = take(win.size() * sizeof(WinItem)), o_pair = take(pair.size() * sizeof(WinItem));
+    const size_t o_done = take(std::max<size_t>(n_runs, 1) * sizeof(int));
+    const size_t total = off;
+    if (total > b->tab_cap) {
+        if (b->tab) (void)hipFree(b->tab);
+        b->tab = nullptr;
+        b->tab_cap = 0;
+        HIP_TRY(hipMalloc(&b->tab, total));
+        b->tab_cap = total;
+    }
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data() + o_runs, descs.data(), n_runs * sizeof(RunDesc));
+    std::memcpy(host.data() + o_sw, sweep.data(), sweep.size() * sizeof(SweepItem));
+    std::memcpy(host.data() + o_win, win.data(), win.size() * sizeof(WinItem));
+    std::memcpy(host.data() + o_pair, pair.data(), pair.size() * sizeof(WinItem));
+    HIP_TRY(hipMemcpyAsync(b->tab, host.data(), total, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    char *t = (char *)b->tab;
+    BatchDev &d = b->dev;
+    d.runs = (const RunDesc *)(t + o_runs);
+    d.sweep = (const SweepItem *)(t + o_sw);
+    d.win = (const WinItem *)(t + o_win);
+    d.pair = (const WinItem *)(t + o_pair);
+    d.n_runs = (int)n_runs;
+    d.n_sweep = (int)sweep.size();
+    d.n_win = (int)win.size();
+    d.n_pair = (int)pair.size();
+    d.P = b->P;
+    d.max_N = max_N;
+    d.max_W = max_W;
+    d.any_ea = any_ea;
+    d.region = (int)sweep_walker_lds(max_W, max_N, kWave / b->P);
+    b->done_d = (int *)(t + o_done);
+    if (b->pinned_cap < std::max<size_t>(n_runs, 1)) {
+        if (b->pinned) (void)hipHostFree(b->pinned);
+        b->pinned = nullptr;
+        b->pinned_cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&b->pinned, std::max<size_t>(n_runs, 1) * sizeof(int)));
+        b->pinned_cap = std::max<size_t>(n_runs, 1);
+    }
+    b->dirty = false;
+    return REWL_OK;
+}
+
+int launch_rounds(rewl_batch *b, int64_t rounds)
+{
+    for (int64_t i = 0; i < rounds; ++i) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (b->timing) {
+            int rc = take_event(b, &e0);
+            if (!rc) rc = take_event(b, &e1);
+            if (rc) return rc;
+        }
+        const int rc = rewl_launch_round(b->dev, b->stream, e0, e1);
+        if (rc) return fail(rc == -1 ? REWL_EINVAL : REWL_EDEVICE, "kernel launch failed");
+        b->rounds += 1;
+    }
+    return REWL_OK;
+}
+
+int batch_step(rewl_batch *b, int64_t rounds)
+{
+    if (rounds < 0) return fail(REWL_EINVAL, "negative rounds");
+    if (b->dirty) {
+        int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    if (b->dev.n_runs == 0) return REWL_OK;
+    const int R = b->graph_rounds;
+    if (R > 0 && !b->timing) {
+        if (!b->graph) {
+            // the null stream cannot be captured: capture on a private stream,
+            // replay on the batch's stream
+            if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = REWL_OK;
+            for (int i = 0; i < R && !rc; ++i)
+                rc = rewl_launch_round(b->dev, b->cap_stream, nullptr, nullptr) ? REWL_EDEVICE : 0;
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+            if (rc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc ? fail(rc, "capture of the round graph failed")
+                          : hip_fail(e, "hipStreamEndCapture");
+            }
+            b->graph_src = g;
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+        while (rounds >= R) {
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+            b->rounds += R;
+            rounds -= R;
+        }
+    }
+    return launch_rounds(b, rounds);
+}
+
+// per-run "all windows done" flags of the batch's live runs, in slot order
+int batch_done(rewl_batch *b, std::vector<int> &flags)
+{
+    if (b->dirty) {
+        int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    flags.assign((size_t)b->dev.n_runs, 0);
+    if (b->dev.n_runs == 0) return REWL_OK;
+    if (rewl_launch_status(b->dev, b->done_d, b->stream)) return fail(REWL_EDEVICE, "status launch");
+    HIP_TRY(hipMemcpyAsync(b->pinned, b->done_d, (size_t)b->dev.n_runs * sizeof(int),
+                           hipMemcpyDeviceToHost, b->stream));
+    int rc = bsync(b);
+    if (rc) return rc;
+    for (int i = 0; i < b->dev.n_runs; ++i) flags[i] = b->pinned[i];
+    return REWL_OK;
+}
+
+// rounds until every live run is done or max_rounds issued; polls after a
+// doubling number of rounds (capped at 64)
+int batch_run(rewl_batch *b, int64_t max_rounds, bool *all)
+{
+    std::vector<int> flags;
+    int rc = batch_done(b, flags);
+    if (rc) return rc;
+    auto every = [&]() {
+        for (int f : flags)
+            if (!f) return false;
+        return true;
+    };
+    int64_t issued = 0, chunk = 4;
+    while (!every() && (max_rounds < 0 || issued < max_rounds)) {
+        int64_t n = chunk;
+        if (max_rounds >= 0) n = std::min(n, max_rounds - issued);
+        rc = batch_step(b, n);
+        if (rc) return rc;
+        issued += n;
+        rc = batch_done(b, flags);
+        if (rc) return rc;
+        chunk = std::min<int64_t>(chunk * 2, 64);
+    }
+    *all = every();
+    return REWL_OK;
+}
+
+void free_run(rewl_ctx *h)
+{
+    if (!h) return;
+    if (h->owns && h->base) (void)hipFree(h->base);
+    delete h;
+}
+
+void free_batch(rewl_batch *b)
+{
+    if (!b) return;
+    if (b->stream || b->tab) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->owns_runs)
+        for (rewl_ctx *r : b->runs) free_run(r);
+    if (b->tab) (void)hipFree(b->tab);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (hipEvent_t e : b->ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_pending) (void)hipEventDestroy(e);
+    delete b;
+}
+
+// Make one run: validate, lay out, allocate (or adopt) its slab, upload its
+// parameters and run the start-up kernel on `stream`.
+int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t buffer_bytes,
+             hipStream_t stream)
+{
+    *out = nullptr;
+    Geometry g;
+    int rc = validate(p, g);
+    if (rc) return rc;
+    rewl_ctx *h = new (std::nothrow) rewl_ctx();
+    if (!h) return fail(REWL_ENOMEM, "host allocation failed");
+    h->p = *p;
+    h->g = g;
+    h->l = layout(p, g);
+    if (p->model == REWL_EA) {
+        h->couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
+        h->p.couplings = h->couplings.data();
+    } else {
+        h->p.couplings = nullptr;
+    }
+    auto bail = [&](int code) {
+        free_run(h);
+        return code;
+    };
+    if (device_buffer) {
+        if (buffer_bytes < h->l.total || ((uintptr_t)device_buffer & 255))
+            return bail(fail(REWL_ENOMEM, "device buffer too small or not 256-byte aligned"));
+        h->base = device_buffer;
+    } else {
+        hipError_t e = hipMalloc(&h->base, h->l.total);
+        if (e != hipSuccess) return bail(fail(REWL_ENOMEM, "hipMalloc of the run state failed"));
+        h->owns = true;
+    }
+    char *b = (char *)h->base;
+    RunDesc &d = h->desc;
+    d.model = p->model;
+    d.L = p->L;
+    d.N = g.N;
+    d.q = (p->model == REWL_POTTS) ? p->q : 2;
+    d.h = p->n_windows;
+    d.m = p->walkers_per_window;
+    d.nw = g.nw;
+    d.Npad = g.Npad;
+    d.Wmax = g.Wmax;
+    d.e_min = (int)g.e_min;
+    d.step = g.step;
+    d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
+    d.key0 = (uint32_t)p->seed;
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.S = p->attempts_per_round;
+    d.flat_p = p->flatness;
+    d.lnf_final = p->lnf_final;
+    d.spins = (int8_t *)(b + h->l.spins);
+    d.E = (int *)(b + h->l.E);
+    d.t = (unsigned long long *)(b + h->l.t);
+    d.flat = (int *)(b + h->l.flat);
+    d.lng = (double *)(b + h->l.lng);
+    d.H = (uint32_t *)(b + h->l.H);
+    d.n_acc = (unsigned long long *)(b + h->l.n_acc);
+    d.lnf = (double *)(b + h->l.lnf);
+    d.done = (int *)(b + h->l.done);
+    d.finish = (long long *)(b + h->l.finish);
+    d.lo = (int *)(b + h->l.lo);
+    d.hi = (int *)(b + h->l.hi);
+    d.ex_prop = (unsigned long long *)(b + h->l.ex_prop);
+    d.ex_acc = (unsigned long long *)(b + h->l.ex_acc);
+    d.J4 = (uint32_t *)(b + h->l.J4);
+    d.round = (long long *)(b + h->l.round);
+    d.status = (int *)(b + h->l.status);
+
+    const int H = p->n_windows, N = g.N, L = p->L;
+    std::vector<double> lnf(H, p->lnf_init);
+    std::vector<long long> fin(H, -1);
+    std::vector<int> lo(H), hi(H);
+    for (int k = 0; k < H; ++k) {
+        lo[k] = (int)g.lo[k];
+        hi[k] = (int)g.hi[k];
+    }
+    std::vector<uint32_t> J4;
+    if (p->model == REWL_EA) {
+        J4.resize(N);
+        const int8_t *J = h->p.couplings;
+        for (int i = 0; i < N; ++i) {
+            const int r = i / L, c = i % L;
+            const int lf = r * L + (c + L - 1) % L, up = ((r + L - 1) % L) * L + c;
+            J4[i] = (uint32_t)(uint8_t)J[2 * i] | ((uint32_t)(uint8_t)J[2 * lf] << 8) |
+                    ((uint32_t)(uint8_t)J[2 * i + 1] << 16) | ((uint32_t)(uint8_t)J[2 * up + 1] << 24);
+        }
+    }
+    hipError_t e = hipMemsetAsync(h->base, 0, h->l.total, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.lnf, lnf.data(), H * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.finish, fin.data(), H * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.lo, lo.data(), H * 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.hi, hi.data(), H * 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !J4.empty())
+        e = hipMemcpyAsync(d.J4, J4.data(), (size_t)N * 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload of the run parameters"));
+    rc = rewl_launch_init(d, stream);
+    if (rc) return bail(fail(REWL_EDEVICE, "launch of the start-up kernel failed"));
+    int status = 0;
+    e = hipMemcpyAsync(&status, d.status, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "start-up"));
+    if (status) return bail(fail(REWL_EINIT, "a walker could not reach its window"));
+    *out = h;
+    return REWL_OK;
+}
+
+rewl_batch *new_batch(hipStream_t stream, int P)
+{
+    rewl_batch *b = new (std::nothrow) rewl_batch();
+    if (!b) return nullptr;
+    b->stream = stream;
+    b->P = P;
+    return b;
+}
+
+bool valid_P(int P) { return P == 1 || P == 2 || P == 4 || P == 8; }
 
 // Join window pieces: for windows k and k+1, among the bins of their overlap
 // visited by both pieces (at or above the previous joining bin), compare the
@@ -303,19 +654,6 @@ int stitch(const rewl_ctx *h, const std::vector<double> &P, double *out)
     return REWL_OK;
 }
 
-int all_done(rewl_ctx *h, bool *done)
-{
-    const int n = h->p.n_windows;
-    HIP_TRY(hipMemcpyAsync(h->pinned, (char *)h->base + h->l.done, (size_t)n * 4,
-                           hipMemcpyDeviceToHost, h->stream));
-    int rc = sync(h);
-    if (rc) return rc;
-    bool all = true;
-    for (int k = 0; k < n; ++k) all = all && h->pinned[k] != 0;
-    *done = all;
-    return REWL_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -328,19 +666,19 @@ int rewl_footprint(const rewl_params *p, size_t *device_bytes, size_t *lds_bytes
     int rc = validate(p, g);
     if (rc) return rc;
     if (device_bytes) *device_bytes = layout(p, g).total;
-    if (lds_bytes) *lds_bytes = sweep_lds_bytes(p->model, g.Wmax, g.N);
+    if (lds_bytes) *lds_bytes = sweep_lds_bytes(1, g.Wmax, g.N, p->model == REWL_EA);
     return REWL_OK;
 }
 
 void rewl_destroy(rewl_ctx *h)
 {
     if (!h) return;
-    if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
-    if (h->owns && h->base) (void)hipFree(h->base);
-    if (h->pinned) (void)hipHostFree(h->pinned);
-    for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
-    for (hipEvent_t e : h->ev_pending) (void)hipEventDestroy(e);
-    delete h;
+    if (h->own_batch) {
+        free_batch(h->batch);  // owns the run
+        return;
+    }
+    if (!h->batch) free_run(h);
+    // runs of a user batch are released with the batch
 }
 
 int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t buffer_bytes,
@@ -348,110 +686,19 @@ int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer, si
 {
     if (!out) return fail(REWL_EINVAL, "out is NULL");
     *out = nullptr;
-    Geometry g;
-    int rc = validate(p, g);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    rewl_ctx *h = nullptr;
+    int rc = make_run(&h, p, device_buffer, buffer_bytes, stream);
     if (rc) return rc;
-    rewl_ctx *h = new (std::nothrow) rewl_ctx();
-    if (!h) return fail(REWL_ENOMEM, "host allocation failed");
-    h->p = *p;
-    h->g = g;
-    h->l = layout(p, g);
-    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    if (p->model == REWL_EA) {
-        h->couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
-        h->p.couplings = h->couplings.data();
-    } else {
-        h->p.couplings = nullptr;
+    rewl_batch *b = new_batch(stream, 1);
+    if (!b) {
+        free_run(h);
+        return fail(REWL_ENOMEM, "host allocation failed");
     }
-    auto bail = [&](int code) {
-        rewl_destroy(h);
-        return code;
-    };
-    if (device_buffer) {
-        if (buffer_bytes < h->l.total || ((uintptr_t)device_buffer & 255))
-            return bail(fail(REWL_ENOMEM, "device buffer too small or not 256-byte aligned"));
-        h->base = device_buffer;
-    } else {
-        hipError_t e = hipMalloc(&h->base, h->l.total);
-        if (e != hipSuccess) return bail(fail(REWL_ENOMEM, "hipMalloc of the run state failed"));
-        h->owns = true;
-    }
-    if (hipHostMalloc((void **)&h->pinned, (size_t)p->n_windows * 4) != hipSuccess)
-        return bail(fail(REWL_ENOMEM, "pinned allocation failed"));
-
-    char *b = (char *)h->base;
-    RunDev &d = h->dev;
-    d.model = p->model;
-    d.L = p->L;
-    d.N = g.N;
-    d.q = (p->model == REWL_POTTS) ? p->q : 2;
-    d.h = p->n_windows;
-    d.m = p->walkers_per_window;
-    d.nw = g.nw;
-    d.Npad = g.Npad;
-    d.Wmax = g.Wmax;
-    d.e_min = (int)g.e_min;
-    d.step = g.step;
-    d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
-    d.S = p->attempts_per_round;
-    d.key0 = (uint32_t)p->seed;
-    d.key1 = (uint32_t)(p->seed >> 32);
-    d.flat_p = p->flatness;
-    d.lnf_final = p->lnf_final;
-    d.spins = (int8_t *)(b + h->l.spins);
-    d.E = (int *)(b + h->l.E);
-    d.t = (unsigned long long *)(b + h->l.t);
-    d.flat = (int *)(b + h->l.flat);
-    d.lng = (double *)(b + h->l.lng);
-    d.H = (uint32_t *)(b + h->l.H);
-    d.n_acc = (unsigned long long *)(b + h->l.n_acc);
-    d.lnf = (double *)(b + h->l.lnf);
-    d.done = (int *)(b + h->l.done);
-    d.finish = (long long *)(b + h->l.finish);
-    d.lo = (int *)(b + h->l.lo);
-    d.hi = (int *)(b + h->l.hi);
-    d.ex_prop = (unsigned long long *)(b + h->l.ex_prop);
-    d.ex_acc = (unsigned long long *)(b + h->l.ex_acc);
-    d.J4 = (uint32_t *)(b + h->l.J4);
-    d.status = (int *)(b + h->l.status);
-
-    // host-side images of the small per-window arrays and the EA couplings
-    const int H = p->n_windows, N = g.N, L = p->L;
-    std::vector<double> lnf(H, p->lnf_init);
-    std::vector<long long> fin(H, -1);
-    std::vector<int> lo(H), hi(H);
-    for (int k = 0; k < H; ++k) {
-        lo[k] = (int)g.lo[k];
-        hi[k] = (int)g.hi[k];
-    }
-    std::vector<uint32_t> J4;
-    if (p->model == REWL_EA) {
-        J4.resize(N);
-        const int8_t *J = h->p.couplings;
-        for (int i = 0; i < N; ++i) {
-            const int r = i / L, c = i % L;
-            const int lf = r * L + (c + L - 1) % L, up = ((r + L - 1) % L) * L + c;
-            J4[i] = (uint32_t)(uint8_t)J[2 * i] | ((uint32_t)(uint8_t)J[2 * lf] << 8) |
-                    ((uint32_t)(uint8_t)J[2 * i + 1] << 16) | ((uint32_t)(uint8_t)J[2 * up + 1] << 24);
-        }
-    }
-    hipError_t e = hipMemsetAsync(h->base, 0, h->l.total, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d.lnf, lnf.data(), H * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d.finish, fin.data(), H * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d.lo, lo.data(), H * 4, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d.hi, hi.data(), H * 4, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess && !J4.empty())
-        e = hipMemcpyAsync(d.J4, J4.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream);
-    if (e != hipSuccess) return bail(hip_fail(e, "upload of the run parameters"));
-    rc = rewl_launch_init(d, h->stream);
-    if (rc) return bail(fail(rc, "launch of the start-up kernel failed"));
-    int status = 0;
-    e = hipMemcpyAsync(&status, d.status, 4, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return bail(hip_fail(e, "start-up"));
-    if (status) return bail(fail(REWL_EINIT, "a walker could not reach its window"));
+    b->runs.push_back(h);
+    b->owns_runs = true;
+    h->batch = b;
+    h->own_batch = true;
     *out = h;
     return REWL_OK;
 }
@@ -480,61 +727,30 @@ int rewl_create(rewl_ctx **out, int model, int L, int q, const int8_t *couplings
 
 int rewl_step(rewl_ctx *h, int64_t rounds)
 {
-    if (!h || rounds < 0) return fail(REWL_EINVAL, "bad handle or negative rounds");
-    for (int64_t i = 0; i < rounds; ++i) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (h->timing) {
-            int rc = take_event(h, &e0);
-            if (!rc) rc = take_event(h, &e1);
-            if (rc) return rc;
-        }
-        int rc = rewl_launch_round(h->dev, h->rounds, h->stream, e0, e1);
-        if (rc) return fail(rc, "kernel launch failed");
-        h->rounds += 1;
-    }
-    return REWL_OK;
+    if (!h || !h->own_batch) return fail(REWL_EINVAL, "bad handle (runs of a batch step with it)");
+    return batch_step(h->batch, rounds);
 }
 
 int rewl_set_timing(rewl_ctx *h, int on)
 {
-    if (!h) return fail(REWL_EINVAL, "bad handle");
-    int rc = sync(h);
-    if (rc) return rc;
-    h->timing = on != 0;
-    h->sweep_ms = 0.0;
-    h->sweep_launches = 0;
-    return REWL_OK;
+    if (!h || !h->batch) return fail(REWL_EINVAL, "bad handle");
+    return rewl_batch_set_timing(h->batch, on);
 }
 
 int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches)
 {
-    if (!h) return fail(REWL_EINVAL, "bad handle");
-    int rc = sync(h);
-    if (rc) return rc;
-    if (sweep_ms) *sweep_ms = h->sweep_ms;
-    if (sweep_launches) *sweep_launches = h->sweep_launches;
-    return REWL_OK;
+    if (!h || !h->batch) return fail(REWL_EINVAL, "bad handle");
+    return rewl_batch_get_timing(h->batch, sweep_ms, sweep_launches);
 }
 
 int rewl_run(rewl_ctx *h, int64_t max_rounds, int64_t *rounds_done)
 {
-    if (!h) return fail(REWL_EINVAL, "bad handle");
+    if (!h || !h->own_batch) return fail(REWL_EINVAL, "bad handle (runs of a batch run with it)");
     bool done = false;
-    int rc = all_done(h, &done);
+    int rc = batch_run(h->batch, max_rounds, &done);
     if (rc) return rc;
-    int64_t issued = 0, chunk = 4;
-    while (!done && (max_rounds < 0 || issued < max_rounds)) {
-        int64_t n = chunk;
-        if (max_rounds >= 0) n = std::min(n, max_rounds - issued);
-        rc = rewl_step(h, n);
-        if (rc) return rc;
-        issued += n;
-        rc = all_done(h, &done);
-        if (rc) return rc;
-        chunk = std::min<int64_t>(chunk * 2, 64);
-    }
     if (rounds_done) {
-        *rounds_done = h->rounds;
+        *rounds_done = h->batch->rounds;
         if (done) {
             std::vector<long long> fin(h->p.n_windows);
             rc = d2h(h, fin.data(), h->l.finish, fin.size());
@@ -613,10 +829,12 @@ int rewl_get_lng(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t
     }
     int rc = stitch(h, P, out);
     if (rc) return rc;
-    bool done = false;
-    rc = all_done(h, &done);
+    std::vector<int> dn(H);
+    rc = d2h(h, dn.data(), h->l.done, (size_t)H);
     if (rc) return rc;
-    return done ? REWL_OK : REWL_NOT_CONVERGED;
+    for (int k = 0; k < H; ++k)
+        if (!dn[k]) return REWL_NOT_CONVERGED;
+    return REWL_OK;
 }
 
 int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step, int *n_windows,
@@ -630,14 +848,16 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
     if (n_windows) *n_windows = h->p.n_windows;
     if (walkers_per_window) *walkers_per_window = h->p.walkers_per_window;
     if (n_sites) *n_sites = h->g.N;
-    if (rounds) *rounds = h->rounds;
     const size_t nw = (size_t)h->g.nw, H = (size_t)h->p.n_windows;
     std::vector<unsigned long long> a(nw), c(nw), xp(H), xa(H);
+    long long r = 0;
     int rc = d2h(h, a.data(), h->l.t, nw);
     if (!rc) rc = d2h(h, c.data(), h->l.n_acc, nw);
     if (!rc) rc = d2h(h, xp.data(), h->l.ex_prop, H);
     if (!rc) rc = d2h(h, xa.data(), h->l.ex_acc, H);
+    if (!rc) rc = d2h(h, &r, h->l.round, 1);
     if (rc) return rc;
+    if (rounds) *rounds = r;
     auto sum = [](const std::vector<unsigned long long> &v) {
         unsigned long long s = 0;
         for (auto x : v) s += x;
@@ -648,6 +868,330 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
     if (ex_prop) *ex_prop = sum(xp);
     if (ex_acc) *ex_acc = sum(xa);
     return REWL_OK;
+}
+
+// ------------------------------------------------------------------ batches
+int rewl_batch_create(rewl_batch **out, const rewl_params *runs, int n_runs, int walkers_per_wave,
+                      void *hip_stream)
+{
+    if (!out || !runs || n_runs < 1) return fail(REWL_EINVAL, "bad arguments");
+    *out = nullptr;
+    const int P = walkers_per_wave > 0 ? walkers_per_wave : 1;
+    if (!valid_P(P)) return fail(REWL_EINVAL, "walkers_per_wave must be 1, 2, 4 or 8");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    rewl_batch *b = new_batch(stream, P);
+    if (!b) return fail(REWL_ENOMEM, "host allocation failed");
+    b->owns_runs = true;
+    for (int i = 0; i < n_runs; ++i) {
+        rewl_ctx *h = nullptr;
+        int rc = make_run(&h, &runs[i], nullptr, 0, stream);
+        if (rc) {
+            free_batch(b);
+            return rc;
+        }
+        h->batch = b;
+        b->runs.push_back(h);
+    }
+    int rc = rebuild(b);
+    if (rc) {
+        free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return REWL_OK;
+}
+
+int rewl_batch_get_run(rewl_batch *b, int i, rewl_ctx **run)
+{
+    if (!b || !run || i < 0 || i >= (int)b->runs.size() || !b->runs[i])
+        return fail(REWL_EINVAL, "bad batch or run index");
+    *run = b->runs[i];
+    return REWL_OK;
+}
+
+int rewl_batch_set_walkers_per_wave(rewl_batch *b, int walkers_per_wave)
+{
+    if (!b || !valid_P(walkers_per_wave)) return fail(REWL_EINVAL, "walkers_per_wave must be 1, 2, 4 or 8");
+    int rc = bsync(b);
+    if (rc) return rc;
+    const int old = b->P;
+    b->P = walkers_per_wave;
+    b->dirty = true;
+    rc = rebuild(b);
+    if (rc) {
+        b->P = old;
+        b->dirty = true;
+        (void)rebuild(b);
+    }
+    return rc;
+}
+
+int rewl_batch_set_graph(rewl_batch *b, int rounds_per_graph)
+{
+    if (!b || rounds_per_graph < 0) return fail(REWL_EINVAL, "bad arguments");
+    int rc = bsync(b);
+    if (rc) return rc;
+    drop_graph(b);
+    b->graph_rounds = rounds_per_graph;
+    return REWL_OK;
+}
+
+int rewl_batch_step(rewl_batch *b, int64_t rounds)
+{
+    if (!b) return fail(REWL_EINVAL, "bad batch");
+    return batch_step(b, rounds);
+}
+
+int rewl_batch_run(rewl_batch *b, int64_t max_rounds, int64_t *rounds_issued)
+{
+    if (!b) return fail(REWL_EINVAL, "bad batch");
+    bool done = false;
+    int rc = batch_run(b, max_rounds, &done);
+    if (rc) return rc;
+    if (rounds_issued) *rounds_issued = b->rounds;
+    return done ? REWL_OK : REWL_NOT_CONVERGED;
+}
+
+int rewl_batch_done(rewl_batch *b, int *flags, int cap)
+{
+    if (!b || !flags) return fail(REWL_EINVAL, "bad arguments");
+    std::vector<int> f;
+    int rc = batch_done(b, f);
+    if (rc) return rc;
+    if (cap < (int)f.size()) return fail(REWL_EINVAL, "flags capacity below the number of runs");
+    for (size_t i = 0; i < f.size(); ++i) flags[i] = f[i];
+    return REWL_OK;
+}
+
+int rewl_batch_set_timing(rewl_batch *b, int on)
+{
+    if (!b) return fail(REWL_EINVAL, "bad batch");
+    int rc = bsync(b);
+    if (rc) return rc;
+    b->timing = on != 0;
+    b->sweep_ms = 0.0;
+    b->sweep_launches = 0;
+    return REWL_OK;
+}
+
+int rewl_batch_get_timing(rewl_batch *b, double *sweep_ms, int64_t *sweep_launches)
+{
+    if (!b) return fail(REWL_EINVAL, "bad batch");
+    int rc = bsync(b);
+    if (rc) return rc;
+    if (sweep_ms) *sweep_ms = b->sweep_ms;
+    if (sweep_launches) *sweep_launches = b->sweep_launches;
+    return REWL_OK;
+}
+
+void rewl_batch_destroy(rewl_batch *b) { free_batch(b); }
+// ------------------------------------------------------------------- server
+}  // extern "C"
+
+struct rewl_server {
+    rewl_batch *batch = nullptr;        // running runs (slots reused)
+    size_t budget = 0, used = 0;        // device bytes
+    int rounds_per_tick = 8;
+    int64_t next_id = 0;
+    struct Pending {
+        int64_t id;
+        rewl_params p;
+        std::vector<int8_t> couplings;
+        size_t bytes;
+    };
+    std::vector<Pending> queue;         // FIFO
+    struct Finished {
+        std::vector<double> lng;
+        int64_t n_bins, e_min, e_step, rounds;
+        int status;
+    };
+    std::map<int64_t, Finished> results;
+    std::vector<int64_t> done_order;    // finished ids not yet popped
+};
+
+namespace {
+
+// retire finished runs: stitch on the host, free their slabs and slots
+int server_retire(rewl_server *s)
+{
+    rewl_batch *b = s->batch;
+    std::vector<int> flags;
+    int rc = batch_done(b, flags);
+    if (rc) return rc;
+    int live = 0;
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+        rewl_ctx *h = b->runs[i];
+        if (!h) continue;
+        const int f = flags[live++];
+        if (!f) continue;
+        rewl_server::Finished fin;
+        fin.lng.assign((size_t)h->g.B, 0.0);
+        fin.status = rewl_get_lng(h, fin.lng.data(), h->g.B, &fin.n_bins, &fin.e_min, &fin.e_step);
+        std::vector<long long> fr(h->p.n_windows);
+        rc = d2h(h, fr.data(), h->l.finish, fr.size());
+        if (rc) return rc;
+        fin.rounds = *std::max_element(fr.begin(), fr.end()) + 1;
+        s->results[h->id] = std::move(fin);
+        s->done_order.push_back(h->id);
+        s->used -= h->l.total;
+        free_run(h);
+        b->runs[i] = nullptr;
+        b->dirty = true;
+    }
+    return REWL_OK;
+}
+
+// largest walkers-per-wave <= want whose LDS footprint fits all runs
+int fit_P(rewl_batch *b, int want, int extra_W, int extra_N, bool extra_ea)
+{
+    int max_W = extra_W, max_N = extra_N;
+    bool ea = extra_ea;
+    for (rewl_ctx *h : b->runs) {
+        if (!h) continue;
+        max_W = std::max(max_W, h->g.Wmax);
+        max_N = std::max(max_N, h->g.N);
+        ea = ea || h->p.model == REWL_EA;
+    }
+    for (int P = want; P >= 1; P /= 2)
+        if (sweep_lds_bytes(P, max_W, max_N, ea) <= kMaxLds) return P;
+    return 0;
+}
+
+// admit queued runs in arrival order while they fit the device budget
+int server_admit(rewl_server *s, int want_P)
+{
+    rewl_batch *b = s->batch;
+    while (!s->queue.empty()) {
+        rewl_server::Pending &q = s->queue.front();
+        if (s->used + q.bytes > s->budget) break;
+        Geometry g;
+        int rc = validate(&q.p, g);
+        if (rc) return rc;
+        const int P = fit_P(b, want_P, g.Wmax, g.N, q.p.model == REWL_EA);
+        if (P == 0) break;
+        rewl_ctx *h = nullptr;
+        rc = make_run(&h, &q.p, nullptr, 0, b->stream);
+        if (rc) return rc;
+        h->batch = b;
+        h->id = q.id;
+        h->admit_round = b->rounds;
+        s->used += h->l.total;
+        size_t slot = 0;
+        while (slot < b->runs.size() && b->runs[slot]) ++slot;
+        if (slot == b->runs.size()) b->runs.push_back(h);
+        else b->runs[slot] = h;
+        b->P = P;
+        b->dirty = true;
+        s->queue.erase(s->queue.begin());
+    }
+    return REWL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rewl_server_create(rewl_server **out, size_t device_budget_bytes, int walkers_per_wave,
+                       int rounds_per_tick, void *hip_stream)
+{
+    if (!out || device_budget_bytes == 0 || rounds_per_tick < 1 ||
+        !valid_P(walkers_per_wave > 0 ? walkers_per_wave : 1))
+        return fail(REWL_EINVAL, "bad server arguments");
+    *out = nullptr;
+    rewl_server *s = new (std::nothrow) rewl_server();
+    if (!s) return fail(REWL_ENOMEM, "host allocation failed");
+    s->batch = new_batch(reinterpret_cast<hipStream_t>(hip_stream),
+                         walkers_per_wave > 0 ? walkers_per_wave : 1);
+    if (!s->batch) {
+        delete s;
+        return fail(REWL_ENOMEM, "host allocation failed");
+    }
+    s->batch->owns_runs = true;
+    s->budget = device_budget_bytes;
+    s->rounds_per_tick = rounds_per_tick;
+    *out = s;
+    return REWL_OK;
+}
+
+int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id)
+{
+    if (!s || !p) return fail(REWL_EINVAL, "bad arguments");
+    Geometry g;
+    int rc = validate(p, g);
+    if (rc) return rc;
+    rewl_server::Pending q;
+    q.id = s->next_id++;
+    q.p = *p;
+    if (p->model == REWL_EA) {
+        q.couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
+        q.p.couplings = q.couplings.data();
+    } else {
+        q.p.couplings = nullptr;
+    }
+    q.bytes = layout(p, g).total;
+    if (q.bytes > s->budget) return fail(REWL_EBUSY, "run larger than the server's device budget");
+    s->queue.push_back(std::move(q));
+    // vector growth moved the couplings; point each entry at its own copy again
+    for (auto &e : s->queue)
+        if (e.p.model == REWL_EA) e.p.couplings = e.couplings.data();
+    if (id) *id = s->queue.back().id;
+    return REWL_OK;
+}
+
+int rewl_server_tick(rewl_server *s, int *n_running, int *n_queued)
+{
+    if (!s) return fail(REWL_EINVAL, "bad server");
+    rewl_batch *b = s->batch;
+    int rc = server_retire(s);
+    if (!rc) rc = server_admit(s, b->P > 0 ? b->P : 1);
+    if (!rc) rc = batch_step(b, s->rounds_per_tick);
+    if (rc) return rc;
+    int running = 0;
+    for (rewl_ctx *h : b->runs) running += h != nullptr;
+    if (n_running) *n_running = running;
+    if (n_queued) *n_queued = (int)s->queue.size();
+    return REWL_OK;
+}
+
+int rewl_server_next_done(rewl_server *s, int64_t *id, int64_t *rounds)
+{
+    if (!s || !id) return fail(REWL_EINVAL, "bad arguments");
+    if (s->done_order.empty()) return REWL_NOT_CONVERGED;
+    *id = s->done_order.front();
+    s->done_order.erase(s->done_order.begin());
+    if (rounds) *rounds = s->results[*id].rounds;
+    return REWL_OK;
+}
+
+int rewl_server_result(rewl_server *s, int64_t id, double *out, int64_t cap, int64_t *n_bins,
+                       int64_t *e_min, int64_t *e_step)
+{
+    if (!s) return fail(REWL_EINVAL, "bad server");
+    auto it = s->results.find(id);
+    if (it == s->results.end()) return fail(REWL_EINVAL, "unknown or unfinished request id");
+    const rewl_server::Finished &f = it->second;
+    if (n_bins) *n_bins = f.n_bins;
+    if (e_min) *e_min = f.e_min;
+    if (e_step) *e_step = f.e_step;
+    if (out) {
+        if (cap < f.n_bins) return fail(REWL_EINVAL, "output capacity below n_bins");
+        std::memcpy(out, f.lng.data(), (size_t)f.n_bins * sizeof(double));
+    }
+    return f.status;
+}
+
+int rewl_server_release(rewl_server *s, int64_t id)
+{
+    if (!s) return fail(REWL_EINVAL, "bad server");
+    s->results.erase(id);
+    return REWL_OK;
+}
+
+void rewl_server_destroy(rewl_server *s)
+{
+    if (!s) return;
+    free_batch(s->batch);
+    delete s;
 }
 
 int rewl_selftest_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n)

@@ -1,7 +1,6 @@
-// rewl_internal.h -- host/device shared layout of one run's device state.
+// rewl_internal.h -- host/device shared layout of the runs' device state.
 //
-// Everything a kernel touches is described by RunDev, passed by value.  All
-// arrays live in one device allocation carved by rewl_api.cpp:
+// Every run lives in one device slab carved by rewl_api.cpp:
 //   spins   nw x Npad int8   (Ising/EA +-1, Potts 0..q-1)
 //   E       nw int32         (current energy)
 //   t       nw uint64        (sweep attempts made = stream-0 Philox counter)
@@ -13,18 +12,23 @@
 //   ex_prop, ex_acc  h uint64 (exchange proposals / acceptances of pair (k,k+1))
 //   J4      N uint32         (EA: couplings to right, left, down, up neighbour,
 //                             one int8 each, packed little-endian)
+//   round   1 int64          (rounds completed; read by the merge and exchange
+//                             kernels, advanced by advance_kernel)
 //   status  1 int32          (start-up failure flag)
+// Kernels see a run through its RunDesc.  A launch covers a batch of runs
+// through three work lists: sweep groups (P walkers of one run per wave),
+// windows (flatness/merge) and window pairs (exchange).
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
 
-struct RunDev {
+struct RunDesc {
     int model, L, N, q, h, m, nw;
     int Npad, Wmax;
     int e_min, step;
     uint32_t l_magic;  // ceil(2^32 / L): row = mulhi(site, l_magic) for site < L*L
-    long long S;
     uint32_t key0, key1;
+    long long S;
     double flat_p, lnf_final;
     int8_t *spins;
     int *E;
@@ -39,12 +43,35 @@ struct RunDev {
     int *lo, *hi;
     unsigned long long *ex_prop, *ex_acc;
     uint32_t *J4;
+    long long *round;
     int *status;
+};
+
+// One wave of the sweep: walkers w0 .. w0 + count - 1 of run `run`.
+struct SweepItem {
+    int run, w0, count, pad;
+};
+// One window of one run (flatness and merge) / one pair slot of one run
+// (exchange: windows k, k+1 with k = 2 * slot + round mod 2).
+struct WinItem {
+    int run, k;
+};
+
+struct BatchDev {
+    const RunDesc *runs;
+    const SweepItem *sweep;
+    const WinItem *win;
+    const WinItem *pair;
+    int n_runs, n_sweep, n_win, n_pair;
+    int P;          // walkers per wave in the sweep (1, 2, 4, 8, 16, 32, 64)
+    int max_N, max_W;
+    int any_ea;
+    int region;     // LDS bytes of one walker's region: sweep_walker_lds(max_W, max_N, 64/P)
 };
 
 // Proposals staged per block of the sweep (one per lane), decoded so that
 // the in-order pass over them needs no unpacking.
-constexpr int kBlock = 64;
+constexpr int kWave = 64;
 struct alignas(16) Prop {
     double thr;        // ln u of the attempt
     int32_t d_off;     // energy change against the block-start configuration
@@ -64,25 +91,34 @@ struct alignas(16) BinRec {
     uint32_t pad;
 };
 
-// LDS bytes of one walker's sweep work-group: bins (16 W), staged proposals,
-// per-site proposal masks (8 N), EA couplings (4 N), spins (N).
-inline size_t sweep_lds_bytes(int model, int W, int N)
+// LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:
+// bins (16 W), G + 2 staged proposals, per-site proposal masks (8 N), spins (N).
+inline size_t sweep_walker_lds(int W, int N, int G)
 {
     size_t b = 0;
     b += (size_t)W * sizeof(BinRec);
-    b += (size_t)(kBlock + 1) * sizeof(Prop);
+    b += (size_t)(G + 2) * sizeof(Prop);
     b += (size_t)N * 8;
-    if (model == 2) b += (size_t)N * 4;
     b += ((size_t)N + 15) & ~(size_t)15;
-    return b;
+    return (b + 15) & ~(size_t)15;
+}
+
+// LDS bytes of one sweep work-group (P walkers, EA couplings shared by the
+// group's run: 4 N).
+inline size_t sweep_lds_bytes(int P, int W, int N, bool ea)
+{
+    return (size_t)P * sweep_walker_lds(W, N, kWave / P) + (ea ? (size_t)N * 4 : 0);
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
 
 // launchers (rewl_kernels.hip)
-int rewl_launch_init(const RunDev &a, void *stream);
-// ev0/ev1 (hipEvent_t or NULL) are recorded right before and after the sweep
-int rewl_launch_round(const RunDev &a, long long round, void *stream, void *ev0, void *ev1);
+int rewl_launch_init(const RunDesc &a, void *stream);
+// One round of every run in the batch: sweep, flatness/merge, exchange,
+// round counters.  ev0/ev1 (hipEvent_t or NULL) bracket the sweep launch.
+int rewl_launch_round(const BatchDev &b, void *stream, void *ev0, void *ev1);
+// per run of the batch: out_d[i] = 1 when every window of run i is done
+int rewl_launch_status(const BatchDev &b, int *out_d, void *stream);
 int rewl_launch_selftest_philox(const uint32_t *ctr_d, uint32_t k0, uint32_t k1, uint32_t *out_d,
                                 int n);
 int rewl_launch_selftest_ln_u(const uint32_t *words_d, double *out_d, int n);

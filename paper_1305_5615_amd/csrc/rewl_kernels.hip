@@ -1,19 +1,22 @@
 // rewl_kernels.hip -- HIP kernels of replica-exchange Wang-Landau for gfx950.
 //
-// One round of a run is three launches on the run's stream:
-//   sweep_kernel       one work-group (one wave) per walker; the walker's
-//                      spins, ln g and H live in LDS for the whole round;
-//                      the 64 lanes draw 64 attempts at a time (Philox, site,
-//                      neighbours, ln u) in parallel and lane 0 then applies
-//                      them in order, which keeps the sequential single-site
-//                      dynamics of the standard WL walk (standard-WL passage);
+// One round of every run of a batch is four launches on the batch's stream:
+//   sweep_kernel<P>    one wave per group of P walkers of one run; each
+//                      walker's spins, ln g and H live in LDS for the round;
+//                      the walker's 64/P lanes draw 64/P attempts at a time
+//                      (Philox, site, neighbours, ln u, energy change) in
+//                      parallel and one lane per walker then applies them in
+//                      order, which keeps the sequential single-site dynamics
+//                      of the standard WL walk (standard-WL paragraph);
 //   flat_merge_kernel  one work-group per window: flatness of each walker,
 //                      and when all m are flat the mean of their ln g, H reset,
-//                      ln f halved (parallel-scheme passage after Eq. (1));
+//                      ln f halved (parallel-scheme paragraph);
 //   exchange_kernel    one work-group per window pair (k, k+1), k = round mod
-//                      2: partner permutation, Eq. (1) test, configuration swap.
-// The start-up step (random configuration, energy, walk into the window) is
-// init_kernel.  Compiled with -ffp-contract=off (see rewl_device.h).
+//                      2: partner permutation, Eq. (1) test, configuration swap;
+//   advance_kernel     each run's round counter + 1.
+// The round number lives on the device, so a captured graph of rounds replays
+// correctly.  The start-up step (random configuration, energy, walk into the
+// window) is init_kernel.  Compiled with -ffp-contract=off (see rewl_device.h).
 #include <hip/hip_runtime.h>
 
 #include "rewl_device.h"
@@ -93,12 +96,12 @@ __device__ int block_sum_256(int v, int *scratch)
 // outside after 200 N moves restart from the ordered state, and a walker still
 // outside after 400 N moves (EA: 200 N) fails the start-up.
 template <int MODEL>
-__global__ __launch_bounds__(256) void init_kernel(RunDev a)
+__global__ __launch_bounds__(256) void init_kernel(RunDesc a)
 {
     const int w = blockIdx.x, k = w / a.m, N = a.N, L = a.L;
     extern __shared__ __align__(16) unsigned char smem[];
     Move *stage = reinterpret_cast<Move *>(smem);
-    int *scratch = reinterpret_cast<int *>(stage + kBlock);   // 8 ints
+    int *scratch = reinterpret_cast<int *>(stage + kWave);   // 8 ints
     uint32_t *J_s = reinterpret_cast<uint32_t *>(scratch + 8);
     int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
     __shared__ int sh_E, sh_stop, sh_used;
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
     const unsigned long long cap = 200ull * (unsigned long long)N;
     unsigned long long d = 0;
     while (!sh_stop) {
-        if (threadIdx.x < kBlock) {
+        if (threadIdx.x < kWave) {
             const unsigned long long c = d + threadIdx.x;
             const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 2u, a.key0, a.key1);
             const int site = (int)mulhi32(r.x, (uint32_t)N);
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
         __syncthreads();
         if (threadIdx.x == 0) {
             int E = sh_E, stop = 0, j = 0;
-            for (; j < kBlock; ++j) {
+            for (; j < kWave; ++j) {
                 if (dist_to(E, elo, ehi) == 0) { stop = 1; break; }
                 const unsigned long long dd = d + j;
                 if (dd == cap) {
@@ -178,13 +181,14 @@ __global__ __launch_bounds__(256) void init_kernel(RunDev a)
 }
 
 // ------------------------------------------------------------------- sweep
-// Attempts are taken 64 at a time.  Lane i draws attempt t+i (Philox stream
-// 0: site, Potts offset, u -> ln u), computes its energy change against the
-// configuration at the start of the block, and flags it when an earlier
-// proposal of the block hits its site or a neighbour (per-site 64-bit masks in
-// LDS).  Lane 0 then applies the 64 attempts in order; a flagged attempt
-// recomputes its energy change from the current spins, every other one uses
-// the precomputed value, so the result is that of the plain sequential walk.
+// Attempts are taken G = 64/P at a time per walker.  Lane g of a walker's
+// group draws attempt t+g (Philox stream 0: site, Potts offset, u -> ln u),
+// computes its energy change against the configuration at the start of the
+// block, and flags it when an earlier proposal of the block hits its site or a
+// neighbour (per-site masks in LDS, set with an atomic OR).  The group's first
+// lane then applies the G attempts in order; a flagged attempt recomputes its
+// energy change from the current spins, every other one uses the precomputed
+// value, so the result is that of the plain sequential walk.
 template <int MODEL>
 __device__ __forceinline__ int new_state(int old, uint32_t r1, int q)
 {
@@ -195,59 +199,67 @@ __device__ __forceinline__ int new_state(int old, uint32_t r1, int q)
     return -old;
 }
 
-template <int MODEL>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
+template <int MODEL, int P>
+__device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
+                                           const BatchDev &bd, unsigned char *smem)
 {
-    const int w = blockIdx.x, k = w / a.m;
-    if (a.done[k]) return;
-    const int lane = threadIdx.x, N = a.N, L = a.L, q = a.q;
+    constexpr int G = kWave / P;
     constexpr int STEP = Step<MODEL>::value;
     constexpr int ADDR_PER_E = (int)sizeof(BinRec) / STEP;
-    const int lo = a.lo[k], W = a.hi[k] - lo + 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    BinRec *bins = reinterpret_cast<BinRec *>(smem);
-    Prop *stage = reinterpret_cast<Prop *>(bins + W);
-    uint64_t *tag = reinterpret_cast<uint64_t *>(stage + kBlock + 1);
-    uint32_t *J_s = reinterpret_cast<uint32_t *>(tag + N);
-    int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
+    const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+    const int N = a.N, L = a.L, q = a.q;
+    const int w = it.w0 + grp;
+    const int k = w / a.m;
+    // a walker group is live when it exists and its window is still running
+    const bool live = grp < it.count && !a.done[k];
+    const size_t region = (size_t)bd.region;
+    unsigned char *mine = smem + (size_t)grp * region;
+    BinRec *bins = reinterpret_cast<BinRec *>(mine);
+    Prop *stage = reinterpret_cast<Prop *>(bins + bd.max_W);
+    uint64_t *tag = reinterpret_cast<uint64_t *>(stage + G + 2);
+    int8_t *sp = reinterpret_cast<int8_t *>(tag + bd.max_N);
+    uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)P * region);
     const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - smem);
 
+    const int lo = live ? a.lo[k] : 0;
+    const int W = live ? a.hi[k] - lo + 1 : 1;
     double *lng_g = a.lng + (size_t)w * a.Wmax;
     uint32_t *H_g = a.H + (size_t)w * a.Wmax;
     int8_t *sp_g = a.spins + (size_t)w * a.Npad;
-    for (int i = lane; i < W; i += kBlock) {
-        bins[i].lng = lng_g[i];
-        bins[i].H = H_g[i];
-    }
-    {
+    if (live) {
+        for (int i = gl; i < W; i += G) {
+            bins[i].lng = lng_g[i];
+            bins[i].H = H_g[i];
+        }
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
-        for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
+        for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
+        for (int i = gl; i < N; i += G) tag[i] = 0ull;
     }
-    for (int i = lane; i < N; i += kBlock) tag[i] = 0ull;
     if (MODEL == kEA)
-        for (int i = lane; i < N; i += kBlock) J_s[i] = a.J4[i];
+        for (int i = lane; i < N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
 
     const int elo = a.e_min + lo * STEP;
     const unsigned span = (unsigned)((W - 1) * STEP);
-    const double lnf = a.lnf[k];
-    const unsigned long long t0 = a.t[w];
+    const double lnf = live ? a.lnf[k] : 0.0;
+    const unsigned long long t0 = live ? a.t[w] : 0ull;
     const long long S = a.S;
     // chain state: energy offset from the window's lowest energy, LDS byte
     // offset of the current bin's record, its ln g
-    int eoff = a.E[w] - elo;
-    uint32_t baddr = (uint32_t)(eoff / STEP) * (uint32_t)sizeof(BinRec);
-    double gcur = bins[eoff / STEP].lng;
+    int eoff = live ? a.E[w] - elo : 0;
+    uint32_t baddr = (uint32_t)((unsigned char *)bins - smem) +
+                     (uint32_t)(eoff / STEP) * (uint32_t)sizeof(BinRec);
+    double gcur = live ? bins[eoff / STEP].lng : 0.0;
     unsigned int acc = 0;
-    const uint64_t bit = 1ull << lane;
+    const uint64_t bit = 1ull << gl;
 
-    for (long long base = 0; base < S; base += kBlock) {
-        const int n = (S - base < kBlock) ? (int)(S - base) : kBlock;
-        const bool active = lane < n;
+    for (long long base = 0; base < S; base += G) {
+        const int n = (S - base < G) ? (int)(S - base) : G;
+        const bool active = live && gl < n;
         int site = 0;
         if (active) {
-            const unsigned long long c = t0 + (unsigned long long)base + lane;
+            const unsigned long long c = t0 + (unsigned long long)base + gl;
             const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
             site = (int)mulhi32(r.x, (uint32_t)N);
             const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(q - 1)) : 0u;
@@ -266,17 +278,15 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
                       ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
             p.site = (uint32_t)site;
             p.pad = 0;
-            stage[lane] = p;
+            stage[gl] = p;
         }
         __syncthreads();
         if (active) tag[site] = 0ull;
-        if (lane == 0) {
+        if (live && gl == 0) {
             // In-order pass, branch-free except for flagged attempts: the
             // candidate bin is clamped into the window so its ln g can always
             // be loaded, H grows with an LDS atomic, and full blocks run
             // unrolled so the staged records load ahead of use.
-            // fields the fast path needs, loaded one attempt ahead; the site
-            // of a flagged attempt is read from LDS only on that slow path
             struct Fast {
                 double thr;
                 int d_off, d_addr;
@@ -320,9 +330,9 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
             // each record is loaded before the previous attempt's LDS stores,
             // which the compiler may not move loads across
             Fast cur = fetch(0);
-            if (n == kBlock) {
+            if (n == G) {
 #pragma unroll
-                for (int j = 0; j < kBlock; ++j) {
+                for (int j = 0; j < G; ++j) {
                     const Fast nxt = fetch(j + 1);
                     // keep the use of the next record out of this attempt, so
                     // its load latency hides behind this attempt's ln g load
@@ -342,19 +352,32 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
         __syncthreads();
     }
 
-    for (int i = lane; i < W; i += kBlock) {
-        lng_g[i] = bins[i].lng;
-        H_g[i] = bins[i].H;
-    }
-    {
+    if (live) {
+        for (int i = gl; i < W; i += G) {
+            lng_g[i] = bins[i].lng;
+            H_g[i] = bins[i].H;
+        }
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
-        for (int i = lane; i < (N + 3) / 4; i += kBlock) dst[i] = src[i];
+        for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
+        if (gl == 0) {
+            a.E[w] = eoff + elo;
+            a.t[w] = t0 + (unsigned long long)S;
+            a.n_acc[w] += acc;
+        }
     }
-    if (lane == 0) {
-        a.E[w] = eoff + elo;
-        a.t[w] = t0 + (unsigned long long)S;
-        a.n_acc[w] += acc;
+}
+
+template <int P>
+__global__ __launch_bounds__(kWave) void sweep_kernel(BatchDev bd)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SweepItem it = bd.sweep[blockIdx.x];
+    const RunDesc a = bd.runs[it.run];
+    switch (a.model) {
+    case kIsing: sweep_body<kIsing, P>(a, it, bd, smem); break;
+    case kPotts: sweep_body<kPotts, P>(a, it, bd, smem); break;
+    default: sweep_body<kEA, P>(a, it, bd, smem); break;
     }
 }
 
@@ -362,10 +385,13 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(RunDev a)
 // flat <=> min H * n >= p * sum H over the walker's visited bins (lng > 0);
 // when all m walkers of the window are flat: ln g <- (sum_s ln g_s) / m summed
 // s = 0..m-1 in order, H <- 0, flags cleared, ln f halved, done below lnf_final.
-__global__ __launch_bounds__(256) void flat_merge_kernel(RunDev a, long long round)
+__global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
 {
-    const int k = blockIdx.x;
+    const WinItem it = bd.win[blockIdx.x];
+    const RunDesc &a = bd.runs[it.run];
+    const int k = it.k;
     if (a.done[k]) return;
+    const long long round = *a.round;
     const int lo = a.lo[k], W = a.hi[k] - lo + 1, m = a.m;
     __shared__ unsigned long long sh_sum[4];
     __shared__ unsigned int sh_min[4], sh_n[4];
@@ -446,9 +472,12 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(RunDev a, long long rou
 // and walker pi[a] of window k+1 (configuration Y) swap configurations iff
 // both energies lie in both windows and
 // ln u < [ln g_i(E_X) - ln g_i(E_Y)] + [ln g_j(E_Y) - ln g_j(E_X)]   (Eq. (1)).
-__global__ __launch_bounds__(256) void exchange_kernel(RunDev a, long long round)
+__global__ __launch_bounds__(256) void exchange_kernel(BatchDev bd)
 {
-    const int k = 2 * (int)blockIdx.x + (int)(round & 1);
+    const WinItem it = bd.pair[blockIdx.x];
+    const RunDesc &a = bd.runs[it.run];
+    const long long round = *a.round;
+    const int k = 2 * it.k + (int)(round & 1);
     if (k + 1 >= a.h) return;
     if (a.done[k] || a.done[k + 1]) return;
     const int m = a.m;
@@ -514,6 +543,24 @@ __global__ __launch_bounds__(256) void exchange_kernel(RunDev a, long long round
     }
 }
 
+// per run: 1 when every window is done
+__global__ void status_kernel(BatchDev bd, int *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= bd.n_runs) return;
+    const RunDesc &a = bd.runs[i];
+    int all = 1;
+    for (int k = 0; k < a.h; ++k) all &= (a.done[k] != 0);
+    out[i] = all;
+}
+
+// every run's round counter + 1 (the oracle counts rounds of finished runs too)
+__global__ void advance_kernel(BatchDev bd)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < bd.n_runs) *bd.runs[i].round += 1;
+}
+
 __global__ void selftest_philox_kernel(const uint32_t *ctr, uint32_t k0, uint32_t k1,
                                        uint32_t *out, int n)
 {
@@ -534,9 +581,9 @@ __global__ void selftest_ln_u_kernel(const uint32_t *words, double *out, int n)
 }
 
 template <int MODEL>
-int launch_init_t(const RunDev &a, hipStream_t s)
+int launch_init_t(const RunDesc &a, hipStream_t s)
 {
-    const size_t lds = kBlock * sizeof(Move) + 8 * sizeof(int) +
+    const size_t lds = kWave * sizeof(Move) + 8 * sizeof(int) +
                        (MODEL == kEA ? (size_t)a.N * 4 : 0) + (size_t)a.N + 16;
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
@@ -546,29 +593,24 @@ int launch_init_t(const RunDev &a, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-template <int MODEL>
-int launch_round_t(const RunDev &a, long long round, hipStream_t s, size_t lds, hipEvent_t e0,
-                   hipEvent_t e1)
+template <int P>
+int launch_sweep_t(const BatchDev &b, hipStream_t s, size_t lds)
 {
-    static size_t lds_set = 64 * 1024;
-    if (lds > lds_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<MODEL>),
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kMaxLds) != hipSuccess)
             return -3;
-        lds_set = kMaxLds;
+        attr_set = true;
     }
-    if (e0 && hipEventRecord(e0, s) != hipSuccess) return -3;
-    hipLaunchKernelGGL(sweep_kernel<MODEL>, dim3(a.nw), dim3(kBlock), lds, s, a);
-    if (e1 && hipEventRecord(e1, s) != hipSuccess) return -3;
-    hipLaunchKernelGGL(flat_merge_kernel, dim3(a.h), dim3(256), 0, s, a, round);
-    hipLaunchKernelGGL(exchange_kernel, dim3((a.h + 1) / 2), dim3(256), 0, s, a, round);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    hipLaunchKernelGGL(sweep_kernel<P>, dim3(b.n_sweep), dim3(kWave), lds, s, b);
+    return 0;
 }
 
 }  // namespace
 
-int rewl_launch_init(const RunDev &a, void *stream)
+int rewl_launch_init(const RunDesc &a, void *stream)
 {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     switch (a.model) {
@@ -578,16 +620,38 @@ int rewl_launch_init(const RunDev &a, void *stream)
     }
 }
 
-int rewl_launch_round(const RunDev &a, long long round, void *stream, void *ev0, void *ev1)
+int rewl_launch_round(const BatchDev &b, void *stream, void *ev0, void *ev1)
 {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0 = reinterpret_cast<hipEvent_t>(ev0), e1 = reinterpret_cast<hipEvent_t>(ev1);
-    const size_t lds = sweep_lds_bytes(a.model, a.Wmax, a.N);
-    switch (a.model) {
-    case kIsing: return launch_round_t<kIsing>(a, round, s, lds, e0, e1);
-    case kPotts: return launch_round_t<kPotts>(a, round, s, lds, e0, e1);
-    default: return launch_round_t<kEA>(a, round, s, lds, e0, e1);
+    const size_t lds = sweep_lds_bytes(b.P, b.max_W, b.max_N, b.any_ea != 0);
+    if (lds > kMaxLds) return -1;
+    if (e0 && hipEventRecord(e0, s) != hipSuccess) return -3;
+    if (b.n_sweep > 0) {
+        int rc;
+        switch (b.P) {
+        case 1: rc = launch_sweep_t<1>(b, s, lds); break;
+        case 2: rc = launch_sweep_t<2>(b, s, lds); break;
+        case 4: rc = launch_sweep_t<4>(b, s, lds); break;
+        case 8: rc = launch_sweep_t<8>(b, s, lds); break;
+        default: return -1;
+        }
+        if (rc) return rc;
     }
+    if (e1 && hipEventRecord(e1, s) != hipSuccess) return -3;
+    if (b.n_win > 0) hipLaunchKernelGGL(flat_merge_kernel, dim3(b.n_win), dim3(256), 0, s, b);
+    if (b.n_pair > 0) hipLaunchKernelGGL(exchange_kernel, dim3(b.n_pair), dim3(256), 0, s, b);
+    if (b.n_runs > 0)
+        hipLaunchKernelGGL(advance_kernel, dim3((b.n_runs + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int rewl_launch_status(const BatchDev &b, int *out_d, void *stream)
+{
+    if (b.n_runs <= 0) return 0;
+    hipLaunchKernelGGL(status_kernel, dim3((b.n_runs + 255) / 256), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), b, out_d);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 int rewl_launch_selftest_philox(const uint32_t *ctr_d, uint32_t k0, uint32_t k1, uint32_t *out_d,

@@ -152,3 +152,128 @@ def test_invalid_arguments_rejected(gpu):
         gpu.Run("ising", 8, n_windows=64)
     with pytest.raises(gpu.RewlError):
         gpu.Run("ising", 8, walkers_per_window=65)
+
+
+# ------------------------------------------------------------------ batches
+MIXED = [
+    dict(model="ising", L=8, n_windows=4, walkers_per_window=2, S=1000, lnf_final=1e-2, seed=21),
+    dict(model="potts", L=10, q=4, n_windows=3, walkers_per_window=4, S=700, lnf_final=1e-2,
+         seed=22),
+    dict(model="ea", L=8, n_windows=5, walkers_per_window=2, S=1000, lnf_final=1e-2, seed=23),
+    dict(model="ising", L=6, n_windows=2, walkers_per_window=1, S=333, lnf_final=1e-2, seed=24),
+]
+
+
+def _mixed():
+    out = []
+    for kw in MIXED:
+        kw = dict(kw)
+        if kw["model"] == "ea":
+            kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+        out.append(kw)
+    return out
+
+
+@pytest.mark.parametrize("P", [1, 2, 4, 8])
+def test_batch_runs_match_oracle(gpu, orc, P):
+    """Runs of different models and sizes in one batch, P walkers per wave:
+    each run equals the same run in the oracle, bit for bit."""
+    runs = _mixed()
+    print("case: mixed batch, walkers per wave", P, flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=P)
+    oracles = [orc.Run(**kw) for kw in runs]
+    for rounds in (1, 6, 30):
+        b.step(rounds)
+        for o in oracles:
+            o.step(rounds)
+        for i, o in enumerate(oracles):
+            assert_same_state(b[i], o, f"batch P={P} run {i}")
+    b.close()
+
+
+def test_batch_graph_replays(gpu, orc):
+    """Rounds replayed from a captured graph, with eager reads between replays,
+    equal the oracle after every replay."""
+    runs = _mixed()
+    print("case: mixed batch with a 4-round graph", flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=2, graph_rounds=4)
+    oracles = [orc.Run(**kw) for kw in runs]
+    for rounds in (4, 4, 6, 8):
+        b.step(rounds)
+        for o in oracles:
+            o.step(rounds)
+        for i, o in enumerate(oracles):
+            assert_same_state(b[i], o, f"graph run {i}")
+    b.close()
+
+
+def test_batch_to_convergence(gpu, orc):
+    """A batch run to convergence: every run done, stitched ln g identical to
+    the oracle's."""
+    runs = _mixed()
+    print("case: mixed batch to convergence", flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=4, graph_rounds=8)
+    ok, _ = b.run()
+    assert ok and b.done().all()
+    for i, kw in enumerate(runs):
+        o = orc.Run(**kw)
+        assert o.run()
+        assert_same_state(b[i], o, f"converged run {i}")
+        lg, lo = b[i].lng(), o.lng()
+        fin = np.isfinite(lo)
+        assert np.array_equal(np.isfinite(lg), fin)
+        assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
+    b.close()
+
+
+def test_batch_full_size_glasses(gpu, orc):
+    """16 +-J 24x24 glasses (8 windows x 4 walkers each), 4 walkers per wave,
+    2 rounds of 10^4 attempts: every run equals the oracle."""
+    runs = [_kw(run_params("ea24", seed=s)) for s in range(16)]
+    print("case: 16 x ea24 batch", flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=4)
+    b.step(2)
+    for i in (0, 7, 15):
+        o = orc.Run(**runs[i], n_threads=0)
+        o.step(2)
+        assert_same_state(b[i], o, f"ea24 run {i}")
+    b.close()
+
+
+# ------------------------------------------------------------------- server
+def test_server_results_equal_alone(gpu, orc):
+    """Runs submitted while others are on the device, admitted at round
+    boundaries under a device budget: each stitched ln g equals the same run
+    alone in the oracle, bit for bit."""
+    reqs = _mixed() + [
+        dict(model="potts", L=6, q=3, n_windows=2, walkers_per_window=2, S=500, lnf_final=3e-2,
+             seed=31),
+        dict(model="ising", L=10, n_windows=3, walkers_per_window=4, S=900, lnf_final=3e-2,
+             seed=32),
+    ]
+    print("case: server with staggered submissions", flush=True)
+    srv = gpu.Server(device_budget_bytes=3 * 1024 * 1024, walkers_per_wave=2, rounds_per_tick=3)
+    ids, done = {}, {}
+    pending = list(range(len(reqs)))
+    ticks = 0
+    while len(done) < len(reqs):
+        if pending and ticks % 2 == 0:
+            i = pending.pop(0)
+            ids[srv.submit(**reqs[i])] = i
+        srv.tick()
+        while True:
+            d = srv.next_done()
+            if d is None:
+                break
+            done[d[0]] = d[1]
+        ticks += 1
+        assert ticks < 5000
+    for rid, i in ids.items():
+        o = orc.Run(**reqs[i])
+        assert o.run()
+        assert done[rid] == max(w["finish_round"] for w in o.windows()) + 1
+        lg, lo = srv.result(rid), o.lng()
+        fin = np.isfinite(lo)
+        assert np.array_equal(np.isfinite(lg), fin), i
+        assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64)), i
+    srv.close()
