@@ -327,7 +327,7 @@ int rebuild(rewl_batch *b)
     d.max_N = max_N;
     d.max_W = max_W;
     d.any_ea = any_ea;
-    d.region = (int)sweep_walker_lds(max_W, max_N, kWave / b->P);
+    d.region = (int)sweep_region(max_W, max_N, kWave / b->P);
     b->done_d = (int *)(t + o_done);
     if (b->pinned_cap < std::max<size_t>(n_runs, 1)) {
         if (b->pinned) (void)hipHostFree(b->pinned);

@@ -66,7 +66,7 @@ struct BatchDev {
     int P;          // walkers per wave in the sweep (1, 2, 4, 8, 16, 32, 64)
     int max_N, max_W;
     int any_ea;
-    int region;     // LDS bytes of one walker's region: sweep_walker_lds(max_W, max_N, 64/P)
+    int region;     // LDS stride of the walkers' regions: sweep_region(max_W, max_N, 64/P)
 };
 
 // Proposals staged per block of the sweep (one per lane), decoded so that
@@ -84,30 +84,34 @@ struct alignas(16) Prop {
     uint32_t pad;
 };
 
-// Per-bin LDS record of the sweep: ln g and H side by side.
-struct alignas(16) BinRec {
-    double lng;
-    uint32_t H;
-    uint32_t pad;
-};
-
 // LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:
-// bins (16 W), G + 2 staged proposals, per-site proposal masks (8 N), spins (N).
+// ln g (8 W), H (4 W), G + 2 staged proposals, per-site G-bit proposal masks
+// (G/8 N), spins (N), each rounded up to 16 bytes.
+inline size_t lds_up16(size_t x) { return (x + 15) & ~(size_t)15; }
 inline size_t sweep_walker_lds(int W, int N, int G)
 {
     size_t b = 0;
-    b += (size_t)W * sizeof(BinRec);
+    b += lds_up16((size_t)W * 8);
+    b += lds_up16((size_t)W * 4);
     b += (size_t)(G + 2) * sizeof(Prop);
-    b += (size_t)N * 8;
-    b += ((size_t)N + 15) & ~(size_t)15;
-    return (b + 15) & ~(size_t)15;
+    b += lds_up16((size_t)N * (size_t)(G / 8));
+    b += lds_up16((size_t)N);
+    return b;
+}
+
+// Stride of the walkers' regions in a work-group: a multiple of 256 bytes plus
+// 32, so the records the groups read at the same offset fall in different
+// LDS banks.
+inline size_t sweep_region(int W, int N, int G)
+{
+    return ((sweep_walker_lds(W, N, G) + 255) & ~(size_t)255) + 32;
 }
 
 // LDS bytes of one sweep work-group (P walkers, EA couplings shared by the
 // group's run: 4 N).
 inline size_t sweep_lds_bytes(int P, int W, int N, bool ea)
 {
-    return (size_t)P * sweep_walker_lds(W, N, kWave / P) + (ea ? (size_t)N * 4 : 0);
+    return (size_t)P * sweep_region(W, N, kWave / P) + (ea ? (size_t)N * 4 : 0);
 }
 
 constexpr size_t kMaxLds = 160 * 1024;

@@ -199,13 +199,36 @@ __device__ __forceinline__ int new_state(int old, uint32_t r1, int q)
     return -old;
 }
 
+// G-bit masks of a block's proposals, one per site
+template <int G> struct TagOf;
+template <> struct TagOf<64> { using T = unsigned long long; };
+template <> struct TagOf<32> { using T = uint32_t; };
+template <> struct TagOf<16> { using T = uint16_t; };
+template <> struct TagOf<8> { using T = uint8_t; };
+
+__device__ __forceinline__ size_t up16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+template <int G>
+__device__ __forceinline__ void tag_set(typename TagOf<G>::T *tag, int site, uint64_t bit)
+{
+    if constexpr (G == 64) {
+        atomicOr(reinterpret_cast<unsigned long long *>(tag) + site, (unsigned long long)bit);
+    } else {
+        // OR into the aligned 32-bit word that holds the site's mask
+        constexpr int per = 32 / G;
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(tag);
+        atomicOr(w32 + site / per, (uint32_t)bit << (G * (site % per)));
+    }
+}
+
 template <int MODEL, int P>
 __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
                                            const BatchDev &bd, unsigned char *smem)
 {
     constexpr int G = kWave / P;
+    using TagT = typename TagOf<G>::T;
     constexpr int STEP = Step<MODEL>::value;
-    constexpr int ADDR_PER_E = (int)sizeof(BinRec) / STEP;
+    constexpr int ADDR_PER_E = 8 / STEP;   // bytes of ln g per energy unit
     const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
     const int N = a.N, L = a.L, q = a.q;
     const int w = it.w0 + grp;
@@ -214,12 +237,16 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const bool live = grp < it.count && !a.done[k];
     const size_t region = (size_t)bd.region;
     unsigned char *mine = smem + (size_t)grp * region;
-    BinRec *bins = reinterpret_cast<BinRec *>(mine);
-    Prop *stage = reinterpret_cast<Prop *>(bins + bd.max_W);
-    uint64_t *tag = reinterpret_cast<uint64_t *>(stage + G + 2);
-    int8_t *sp = reinterpret_cast<int8_t *>(tag + bd.max_N);
+    double *lng_s = reinterpret_cast<double *>(mine);
+    uint32_t *H_s = reinterpret_cast<uint32_t *>(mine + up16((size_t)bd.max_W * 8));
+    Prop *stage = reinterpret_cast<Prop *>(reinterpret_cast<unsigned char *>(H_s) +
+                                           up16((size_t)bd.max_W * 4));
+    TagT *tag = reinterpret_cast<TagT *>(stage + G + 2);
+    int8_t *sp = reinterpret_cast<int8_t *>(reinterpret_cast<unsigned char *>(tag) +
+                                            up16((size_t)bd.max_N * sizeof(TagT)));
     uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)P * region);
     const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - smem);
+    const uint32_t lng_base = (uint32_t)(reinterpret_cast<unsigned char *>(lng_s) - smem);
 
     const int lo = live ? a.lo[k] : 0;
     const int W = live ? a.hi[k] - lo + 1 : 1;
@@ -228,14 +255,15 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     int8_t *sp_g = a.spins + (size_t)w * a.Npad;
     if (live) {
         for (int i = gl; i < W; i += G) {
-            bins[i].lng = lng_g[i];
-            bins[i].H = H_g[i];
+            lng_s[i] = lng_g[i];
+            H_s[i] = H_g[i];
         }
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
-        for (int i = gl; i < N; i += G) tag[i] = 0ull;
+        for (int i = gl; i < N; i += G) tag[i] = (TagT)0;
     }
+    if (gl < 2) stage[G + gl] = Prop{0.0, 0, 0, sp_base, 0u, 0u, 0u};
     if (MODEL == kEA)
         for (int i = lane; i < N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
@@ -245,60 +273,88 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const double lnf = live ? a.lnf[k] : 0.0;
     const unsigned long long t0 = live ? a.t[w] : 0ull;
     const long long S = a.S;
-    // chain state: energy offset from the window's lowest energy, LDS byte
-    // offset of the current bin's record, its ln g
+    // chain state, identical in every lane of the group: energy offset from
+    // the window's lowest energy, LDS byte offset of the current bin's ln g,
+    // its value
     int eoff = live ? a.E[w] - elo : 0;
-    uint32_t baddr = (uint32_t)((unsigned char *)bins - smem) +
-                     (uint32_t)(eoff / STEP) * (uint32_t)sizeof(BinRec);
-    double gcur = live ? bins[eoff / STEP].lng : 0.0;
+    uint32_t baddr = lng_base + (uint32_t)(eoff / STEP) * 8u;
+    double gcur = live ? lng_s[eoff / STEP] : 0.0;
     unsigned int acc = 0;
     const uint64_t bit = 1ull << gl;
+
+    // state-independent part of an attempt: Philox draw, site, neighbours,
+    // Potts offset, ln u
+    struct Draw {
+        int site, rt, lf, dn, up;
+        uint32_t r1;
+        double thr;
+    };
+    auto draw = [&](long long base) {
+        Draw d;
+        const unsigned long long c = t0 + (unsigned long long)base + gl;
+        const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
+        d.site = (int)mulhi32(r.x, (uint32_t)N);
+        d.r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(q - 1)) : 0u;
+        const Nbrs nb = neighbours(d.site, L, N, a.l_magic);
+        d.rt = nb.rt;
+        d.lf = nb.lf;
+        d.dn = nb.dn;
+        d.up = nb.up;
+        d.thr = ln_u(r.z, r.w);
+        return d;
+    };
+    Draw cur = draw(0);
 
     for (long long base = 0; base < S; base += G) {
         const int n = (S - base < G) ? (int)(S - base) : G;
         const bool active = live && gl < n;
-        int site = 0;
+        // state-dependent part, against the configuration at the block start
         if (active) {
-            const unsigned long long c = t0 + (unsigned long long)base + gl;
-            const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
-            site = (int)mulhi32(r.x, (uint32_t)N);
-            const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(q - 1)) : 0u;
-            const Nbrs nb = neighbours(site, L, N, a.l_magic);
-            const int old = sp[site];
-            const int nw = new_state<MODEL>(old, r1, q);
-            const int dE = delta_e<MODEL>(sp, J_s, site, nb.rt, nb.lf, nb.dn, nb.up, old, nw);
-            atomicOr(reinterpret_cast<unsigned long long *>(&tag[site]), (unsigned long long)bit);
-            const uint64_t seen = tag[site] | tag[nb.rt] | tag[nb.lf] | tag[nb.dn] | tag[nb.up];
+            const int old = sp[cur.site];
+            const int nw = new_state<MODEL>(old, cur.r1, q);
+            const int dE = delta_e<MODEL>(sp, J_s, cur.site, cur.rt, cur.lf, cur.dn, cur.up, old, nw);
+            tag_set<G>(tag, cur.site, bit);
+            const uint64_t seen = (uint64_t)tag[cur.site] | tag[cur.rt] | tag[cur.lf] | tag[cur.dn] |
+                                  tag[cur.up];
             Prop p;
-            p.thr = ln_u(r.z, r.w);
+            p.thr = cur.thr;
             p.d_off = dE;
             p.d_addr = dE * ADDR_PER_E;
-            p.sp_off = sp_base + (uint32_t)site;
-            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (r1 << 16) |
+            p.sp_off = sp_base + (uint32_t)cur.site;
+            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (cur.r1 << 16) |
                       ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
-            p.site = (uint32_t)site;
+            p.site = (uint32_t)cur.site;
             p.pad = 0;
             stage[gl] = p;
+        } else {
+            // records past the last attempt: a zero move, read ahead only
+            stage[gl] = Prop{0.0, 0, 0, sp_base, 0u, 0u, 0u};
         }
         __syncthreads();
-        if (active) tag[site] = 0ull;
-        if (live && gl == 0) {
-            // In-order pass, branch-free except for flagged attempts: the
-            // candidate bin is clamped into the window so its ln g can always
-            // be loaded, H grows with an LDS atomic, and full blocks run
-            // unrolled so the staged records load ahead of use.
+        if (active) tag[cur.site] = (TagT)0;
+        // draws of the next block do not depend on the walk and overlap with it
+        const Draw nxt_draw = draw(base + G);
+        uint32_t hb = baddr;  // bin this lane's attempt ends in (for H)
+        if (live) {
+            // In-order pass, executed identically by every lane of the group;
+            // branch-free except for flagged attempts.  The candidate bin is
+            // clamped into the window so its ln g can always be loaded; each
+            // record is loaded before the previous attempt's LDS stores, which
+            // the compiler may not move loads across.
             struct Fast {
                 double thr;
                 int d_off, d_addr;
                 uint32_t sp_off, flags;
             };
             auto fetch = [&](int j) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(&stage[j]);
+                const uint2 u = *reinterpret_cast<const uint2 *>(&stage[j].sp_off);
                 Fast f;
-                f.thr = stage[j].thr;
-                f.d_off = stage[j].d_off;
-                f.d_addr = stage[j].d_addr;
-                f.sp_off = stage[j].sp_off;
-                f.flags = stage[j].flags;
+                f.thr = __hiloint2double((int)v.y, (int)v.x);
+                f.d_off = (int)v.z;
+                f.d_addr = (int)v.w;
+                f.sp_off = u.x;
+                f.flags = u.y;
                 return f;
             };
             auto attempt = [&](const Fast &p, int j) {
@@ -325,37 +381,34 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 acc += accept ? 1u : 0u;
                 gcur = gcur + lnf;
                 *reinterpret_cast<double *>(smem + baddr) = gcur;
-                atomicAdd(reinterpret_cast<uint32_t *>(smem + baddr + 8), 1u);
+                hb = (gl == j) ? baddr : hb;
             };
-            // each record is loaded before the previous attempt's LDS stores,
-            // which the compiler may not move loads across
-            Fast cur = fetch(0);
+            Fast f = fetch(0);
             if (n == G) {
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
-                    const Fast nxt = fetch(j + 1);
-                    // keep the use of the next record out of this attempt, so
-                    // its load latency hides behind this attempt's ln g load
-                    __builtin_amdgcn_sched_barrier(0);
-                    attempt(cur, j);
-                    __builtin_amdgcn_sched_barrier(0);
-                    cur = nxt;
+                    const Fast f1 = fetch(j + 1);
+                    attempt(f, j);
+                    f = f1;
                 }
             } else {
                 for (int j = 0; j < n; ++j) {
-                    const Fast nxt = fetch(j + 1);
-                    attempt(cur, j);
-                    cur = nxt;
+                    const Fast f1 = fetch(j + 1);
+                    attempt(f, j);
+                    f = f1;
                 }
             }
         }
+        // H of the block's attempts, one atomic per lane
+        if (active) atomicAdd(&H_s[(hb - lng_base) >> 3], 1u);
+        cur = nxt_draw;
         __syncthreads();
     }
 
     if (live) {
         for (int i = gl; i < W; i += G) {
-            lng_g[i] = bins[i].lng;
-            H_g[i] = bins[i].H;
+            lng_g[i] = lng_s[i];
+            H_g[i] = H_s[i];
         }
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
