@@ -85,13 +85,14 @@ struct alignas(16) Prop {
 };
 
 // LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:
-// ln g (8 W), H (4 W), G + 2 staged proposals, per-site G-bit proposal masks
-// (G/8 N), spins (N), each rounded up to 16 bytes.
+// ln g (8 (W + 8), with 4 guard bins on either side), H (4 W), G + 2 staged
+// proposals, per-site G-bit proposal masks (G/8 N), spins (N), each rounded up
+// to 16 bytes.
 inline size_t lds_up16(size_t x) { return (x + 15) & ~(size_t)15; }
 inline size_t sweep_walker_lds(int W, int N, int G)
 {
     size_t b = 0;
-    b += lds_up16((size_t)W * 8);
+    b += lds_up16((size_t)(W + 8) * 8);
     b += lds_up16((size_t)W * 4);
     b += (size_t)(G + 2) * sizeof(Prop);
     b += lds_up16((size_t)N * (size_t)(G / 8));

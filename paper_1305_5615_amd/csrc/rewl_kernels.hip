@@ -221,6 +221,10 @@ __device__ __forceinline__ void tag_set(typename TagOf<G>::T *tag, int site, uin
     }
 }
 
+// guard bins on either side of a window's ln g: the largest single-site
+// energy change is 8 (Ising, +-J: 2 bins of 4) or 4 (Potts: 4 bins of 1)
+constexpr int kGuard = 4;
+
 template <int MODEL, int P>
 __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
                                            const BatchDev &bd, unsigned char *smem)
@@ -237,8 +241,10 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const bool live = grp < it.count && !a.done[k];
     const size_t region = (size_t)bd.region;
     unsigned char *mine = smem + (size_t)grp * region;
-    double *lng_s = reinterpret_cast<double *>(mine);
-    uint32_t *H_s = reinterpret_cast<uint32_t *>(mine + up16((size_t)bd.max_W * 8));
+    // ln g of the window with kGuard bins of +inf on either side: a move that
+    // leaves the window meets +inf and is rejected by the ordinary test
+    double *lng_s = reinterpret_cast<double *>(mine) + kGuard;
+    uint32_t *H_s = reinterpret_cast<uint32_t *>(mine + up16((size_t)(bd.max_W + 2 * kGuard) * 8));
     Prop *stage = reinterpret_cast<Prop *>(reinterpret_cast<unsigned char *>(H_s) +
                                            up16((size_t)bd.max_W * 4));
     TagT *tag = reinterpret_cast<TagT *>(stage + G + 2);
@@ -258,6 +264,10 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             lng_s[i] = lng_g[i];
             H_s[i] = H_g[i];
         }
+        if (gl < kGuard) {
+            lng_s[-1 - gl] = __builtin_inf();
+            lng_s[W + gl] = __builtin_inf();
+        }
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
@@ -269,16 +279,14 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     __syncthreads();
 
     const int elo = a.e_min + lo * STEP;
-    const unsigned span = (unsigned)((W - 1) * STEP);
     const double lnf = live ? a.lnf[k] : 0.0;
     const unsigned long long t0 = live ? a.t[w] : 0ull;
     const long long S = a.S;
-    // chain state, identical in every lane of the group: energy offset from
-    // the window's lowest energy, LDS byte offset of the current bin's ln g,
-    // its value
-    int eoff = live ? a.E[w] - elo : 0;
-    uint32_t baddr = lng_base + (uint32_t)(eoff / STEP) * 8u;
-    double gcur = live ? lng_s[eoff / STEP] : 0.0;
+    // chain state, identical in every lane of the group: LDS byte offset of
+    // the current bin's ln g, and its value
+    const int b0 = live ? (a.E[w] - elo) / STEP : 0;
+    uint32_t baddr = lng_base + (uint32_t)b0 * 8u;
+    double gcur = live ? lng_s[b0] : 0.0;
     unsigned int acc = 0;
     const uint64_t bit = 1ull << gl;
 
@@ -358,7 +366,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 return f;
             };
             auto attempt = [&](const Fast &p, int j) {
-                int d_off = p.d_off, d_addr = p.d_addr;
+                int d_addr = p.d_addr;
                 int nw = (int)(int8_t)(p.flags & 0xFFu);
                 int old = (int)(int8_t)((p.flags >> 8) & 0xFFu);
                 if (p.flags & 0x80000000u) {
@@ -366,16 +374,15 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                     const Nbrs nb = neighbours(s, L, N, a.l_magic);
                     old = sp[s];
                     nw = new_state<MODEL>(old, (p.flags >> 16) & 0x7Fu, q);
-                    d_off = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, old, nw);
-                    d_addr = d_off * ADDR_PER_E;
+                    d_addr = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, old, nw) *
+                             ADDR_PER_E;
                 }
-                const int off = eoff + d_off;
-                const bool inwin = (unsigned)off <= span;
-                const uint32_t naddr = inwin ? baddr + (uint32_t)d_addr : baddr;
+                // outside the window the target holds +inf: gcur - gn = -inf
+                // never exceeds ln u, so the move is rejected
+                const uint32_t naddr = baddr + (uint32_t)d_addr;
                 const double gn = *reinterpret_cast<const double *>(smem + naddr);
-                const bool accept = inwin & (gcur - gn > p.thr);
+                const bool accept = gcur - gn > p.thr;
                 smem[p.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
-                eoff = accept ? off : eoff;
                 baddr = accept ? naddr : baddr;
                 gcur = accept ? gn : gcur;
                 acc += accept ? 1u : 0u;
@@ -414,7 +421,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
         if (gl == 0) {
-            a.E[w] = eoff + elo;
+            a.E[w] = elo + (int)((baddr - lng_base) >> 3) * STEP;
             a.t[w] = t0 + (unsigned long long)S;
             a.n_acc[w] += acc;
         }
