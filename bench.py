@@ -1,24 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark: replica-exchange Wang-Landau on one MI355X.
 
-One step = one complete REWL run of the workload: start-up on the device,
-rounds until every window has reached ln f_final, stitching of ln g on the
-host.  Each step uses a fresh seed.  Reported:
-  value        sweep attempts per second over the timed steps (every attempt
-               counts, accepted or not), wall clock around all timed steps;
-  time_to_dos  per-run seconds from creation to the stitched ln g on the host
-               (p50 / p99 over the steps);
-  roofline     the sweep kernel's VALU work per attempt times the attempts it
-               made, over its own time measured with HIP events on the run's
-               stream (rewl_set_timing), against the MI355X vector-ALU peak;
-  cpu_baseline the CPU oracle on a bounded sample of the same workload, all
-               host cores.
+One step = one complete REWL run of the workload (default: 2D Ising 32x32,
+16 windows x 4 walkers): start-up on the device, rounds until every window has
+reached ln f_final, stitching of ln g on the host; fresh seed per step.
+
+Reported on one JSON line:
+  value         sweep attempts per second (every attempt, accepted or not,
+                start-up excluded) over the timed plain steps, wall clock;
+  time_to_dos_s p50 / p99 seconds from creation to the stitched ln g on the
+                host, plain form;
+  batched       the same workload, `--batch` seeds at once in one batch
+                (walkers per wave chosen by the autotuner): aggregate
+                attempts/s and per-run time-to-DOS p50 / p99;
+  roofline      the sweep kernel's VALU work per attempt times its attempts,
+                over its own time measured with HIP events recorded on the run's
+                stream around each sweep launch, against the MI355X vector-ALU
+                peak;
+  cpu_baseline  the CPU oracle on the same workload, all host cores, on a
+                bounded sample of rounds; its time-to-DOS is extrapolated
+                exactly: the oracle is bit-identical to the GPU run, so it makes
+                the same rounds with the same windows active, and its OpenMP
+                static schedule gives each round's time from the per-thread
+                rate.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ising32]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -48,6 +59,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("rewl_kernels.hip", "rewl_device.h", "rewl_internal.h")
+
+
+def kernel_sources_hash():
+    """sha256 over the device sources; a stored counter profile applies to the
+    kernels only while this hash is unchanged."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1305_5615_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(tag):
+    """HBM bytes per sweep launch from profiles/sweep_<tag>.md (FETCH_SIZE and
+    WRITE_SIZE scaled by a device copy of known size), or None when the file is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{tag}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch",
+                                                      "kernel_sources_sha256"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def percentile(xs, q):
     import numpy as np
 
@@ -61,14 +106,15 @@ def run_kwargs(p):
 
 
 def gpu_full_run(rewl, p, max_rounds):
-    """One complete run; returns (seconds, attempts, rounds, sweep_ms, launches, converged)."""
+    """One complete plain run.  Returns a dict with seconds, attempts, rounds,
+    sweep time and launches, convergence, and each window's finishing round."""
     import torch
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = rewl.Run(**run_kwargs(p))
     r.set_timing(True)
-    ok, issued = False, 0
+    ok, issued, rounds = False, 0, 0
     while not ok and issued < max_rounds:
         chunk = min(2000, max_rounds - issued)
         ok, rounds = r.run(chunk)
@@ -79,16 +125,77 @@ def gpu_full_run(rewl, p, max_rounds):
     t1 = time.perf_counter()
     ms, n = r.timing()
     info = r.info()
+    finish = [w["finish_round"] for w in r.windows()]
     r.close()
     assert lng.shape[0] == info["n_bins"]
-    return t1 - t0, info["attempts"], rounds, ms, n, ok
+    return dict(seconds=t1 - t0, attempts=info["attempts"], rounds=rounds, sweep_ms=ms,
+                launches=n, converged=ok, finish=finish)
 
 
-def cpu_baseline(p, seconds):
-    """The oracle on the same workload: start-up, then rounds until ~`seconds`."""
+def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
+    """All runs in one batch; a run's time-to-DOS is the wall clock once the
+    first poll that sees it done has its stitched ln g on the host."""
+    import numpy as np
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=walkers_per_wave,
+                   graph_rounds=graph_rounds)
+    done_at = [None] * len(params)
+    issued, chunk = 0, 64
+    while issued < max_rounds:
+        b.step(chunk)
+        issued += chunk
+        d = b.done()
+        for i in np.nonzero(d)[0]:
+            if done_at[i] is None:
+                b[int(i)].lng()
+                done_at[i] = time.perf_counter() - t0
+        if d.all():
+            break
+        if issued % 8192 == 0:
+            log(f"  ... batched: {issued} rounds, {int(d.sum())}/{len(params)} runs done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    attempts = sum(b[i].info()["attempts"] for i in range(len(params)))
+    b.close()
+    return dict(wall=wall, attempts=attempts, done_at=done_at)
+
+
+def autotune(rewl, params, candidates=(1, 2, 4, 8), rounds=6):
+    """Walkers per wave with the highest attempts/s over a few rounds of this
+    batch (results do not depend on the choice)."""
+    import torch
+
+    best, best_rate = 1, -1.0
+    b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=1)
+    for P in candidates:
+        try:
+            b.set_walkers_per_wave(P)
+        except rewl.RewlError:
+            continue
+        b.step(1)
+        torch.cuda.synchronize()
+        a0 = sum(b[i].info()["attempts"] for i in range(len(params)))
+        t0 = time.perf_counter()
+        b.step(rounds)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rate = (sum(b[i].info()["attempts"] for i in range(len(params))) - a0) / dt
+        log(f"autotune: walkers per wave {P}: {rate / 1e9:.3f} G attempts/s")
+        if rate > best_rate:
+            best, best_rate = P, rate
+    b.close()
+    return best
+
+
+def cpu_baseline(p, seconds, finish, threads):
+    """The oracle on the same workload with `threads` OpenMP threads over its
+    first rounds (all windows active); the time-to-DOS follows from its
+    per-walker round time and the static schedule over the GPU run's rounds."""
     from oracle import core
 
-    threads = os.cpu_count() or 1
     o = core.Run(**run_kwargs(p), n_threads=threads)
     a0 = o.stats()["attempts"]
     t0 = time.perf_counter()
@@ -100,10 +207,134 @@ def cpu_baseline(p, seconds):
         if el >= seconds or o.info()["done"]:
             break
     att = o.stats()["attempts"] - a0
+    nw = p["n_windows"] * p["walkers_per_window"]
+    m = p["walkers_per_window"]
+    chunk = math.ceil(nw / threads)                   # walkers per thread, static schedule
+    per_walker_round = el / rounds / chunk            # one walker's S attempts on one thread
+    total = 0.0
+    edges = sorted(set([0] + [f + 1 for f in finish]))
+    for r0, r1 in zip(edges, edges[1:]):
+        per_thread = [0] * threads
+        for w in range(nw):
+            if finish[w // m] >= r0:
+                per_thread[w // chunk] += 1
+        total += (r1 - r0) * max(per_thread) * per_walker_round
     return {"value": att / el, "unit": "attempts/s", "cores": threads, "kind": "oracle",
             "sample": f"{p['name']} seed {p['seed']}: first {rounds} rounds after start-up "
-                      f"({att} sweep attempts, {el:.1f} s, OpenMP over walkers)",
-            "seconds_per_round": el / rounds}
+                      f"({att} sweep attempts in {el:.1f} s, OpenMP static over {nw} walkers)",
+            "time_to_dos_s_extrapolated": total}
+
+
+def profile(rewl, args, run_params):
+    """Fixed rounds of one run (or of a batch) after start-up, for profilers."""
+    import torch
+
+    if args.batch > 1 and args.walkers_per_wave > 0:
+        runs = [run_kwargs(run_params(args.workload, seed=1 + i)) for i in range(args.batch)]
+        P = args.walkers_per_wave
+        r = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
+        label = f"{len(runs)} x {args.workload}, P={P}"
+        views = [r[i] for i in range(len(runs))]
+    else:
+        r = rewl.Run(**run_kwargs(run_params(args.workload, seed=1)))
+        label = args.workload
+        views = [r]
+    r.set_timing(True)
+    r.step(1)
+    torch.cuda.synchronize()
+    a0 = sum(v.info()["attempts"] for v in views)
+    ms0, n0 = r.timing()
+    t0 = time.perf_counter()
+    r.step(args.rounds)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n = r.timing()
+    att = sum(v.info()["attempts"] for v in views) - a0
+    log(f"profile: {label}, {args.rounds} rounds, {att} attempts, {dt:.3f} s, "
+        f"{att / dt / 1e9:.3f} G attempts/s, sweep avg {1e3 * (ms - ms0) / max(n - n0, 1):.1f} us")
+    r.close()
+
+
+def served(rewl, args):
+    """The served workload: Poisson arrivals of mixed REWL requests, once through
+    the continuous-batching server and once as plain runs in arrival order (FIFO,
+    one run on the device at a time).  Latency = finish - arrival."""
+    import numpy as np
+    import torch
+
+    from workloads import served_stream
+
+    reqs = served_stream(args.served, args.rate, seed=7, lnf_choices=(1e-3, 1e-4),
+                         sizes=args.served_sizes)
+    kinds = [r["params"] for r in reqs]
+
+    # plain FIFO
+    t0 = time.perf_counter()
+    fifo_lat, fifo_att = [], 0
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if now < r["arrival"]:
+            time.sleep(r["arrival"] - now)
+        run = rewl.Run(**run_kwargs(r["params"]))
+        run.run()
+        run.lng()
+        fifo_att += run.info()["attempts"]
+        run.close()
+        fifo_lat.append(time.perf_counter() - t0 - r["arrival"])
+    fifo_wall = time.perf_counter() - t0
+    log(f"served: FIFO {len(reqs)} runs in {fifo_wall:.1f} s")
+
+    # continuous batching
+    srv = rewl.Server(device_budget_bytes=args.budget_mb << 20,
+                      walkers_per_wave=args.walkers_per_wave or 2, rounds_per_tick=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pending = list(range(len(reqs)))
+    ids, lat = {}, {}
+    while len(lat) < len(reqs):
+        now = time.perf_counter() - t0
+        while pending and reqs[pending[0]]["arrival"] <= now:
+            i = pending.pop(0)
+            ids[srv.submit(**run_kwargs(reqs[i]["params"]))] = i
+        running, queued = srv.tick()
+        while True:
+            d = srv.next_done()
+            if d is None:
+                break
+            i = ids[d[0]]
+            srv.result(d[0])
+            srv.release(d[0])
+            lat[i] = time.perf_counter() - t0 - reqs[i]["arrival"]
+        if running == 0 and queued == 0 and pending:
+            time.sleep(max(0.0, reqs[pending[0]]["arrival"] - (time.perf_counter() - t0)))
+    srv_wall = time.perf_counter() - t0
+    srv.close()
+    att = fifo_att  # the served runs are bit-identical to the plain ones: same attempts
+    out = {
+        "metric": "served REWL stream: p50/p99 latency, continuous batching vs plain FIFO",
+        "requests": len(reqs), "rate_per_s": args.rate, "sizes": args.served_sizes,
+        "lnf_final": [1e-3, 1e-4],
+        "mix": {m: sum(1 for k in kinds if k["model"] == m) for m in ("ising", "potts", "ea")},
+        "served": {"p50_s": percentile(list(lat.values()), 50),
+                   "p99_s": percentile(list(lat.values()), 99), "wall_s": srv_wall,
+                   "attempts_per_s": att / srv_wall},
+        "fifo": {"p50_s": percentile(fifo_lat, 50), "p99_s": percentile(fifo_lat, 99),
+                 "wall_s": fifo_wall, "attempts_per_s": att / fifo_wall},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(mb):
+    """One device-to-device copy of `mb` MiB (read mb, write mb) for scaling
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    src = torch.ones(mb << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy: {mb} MiB read, {mb} MiB written")
 
 
 def main():
@@ -112,15 +343,25 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="ising32", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--max-rounds", type=int, default=200000)
+    ap.add_argument("--max-rounds", type=int, default=400000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="runs in the batched comparison (0: skip); in profile mode with "
+                         "--walkers-per-wave, the batch size")
+    ap.add_argument("--walkers-per-wave", type=int, default=0,
+                    help="batched form: walkers per wave (0: autotune)")
+    ap.add_argument("--graph", type=int, default=16, help="batched form: rounds per graph")
     ap.add_argument("--rounds", type=int, default=0,
-                    help="profile mode: one run, this many rounds after start-up, then exit")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="profile mode: this many runs of the workload (seeds 1..n) in one batch")
-    ap.add_argument("--walkers-per-wave", type=int, default=1)
-    ap.add_argument("--graph", type=int, default=0)
+                    help="profile mode: run this many rounds after start-up, then exit")
+    ap.add_argument("--served", type=int, default=0,
+                    help="served mode: this many Poisson-arriving requests")
+    ap.add_argument("--rate", type=float, default=2.0, help="served mode: arrivals per second")
+    ap.add_argument("--served-sizes", default="small", choices=("small", "full"),
+                    help="served mode: lattice sizes of the request mix")
+    ap.add_argument("--budget-mb", type=int, default=4096, help="served mode: device budget")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="counter calibration: one device copy of this many MiB")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: each REWL run lives on one device and "
@@ -134,76 +375,51 @@ def main():
     import paper_1305_5615_amd as rewl
     from workloads import run_params
 
+    if args.rounds > 0:
+        profile(rewl, args, run_params)
+        return
+    if args.served > 0:
+        served(rewl, args)
+        return
+    if args.copy_mb > 0:
+        calibrate_copy(args.copy_mb)
+        return
+
     base = dict(run_params(args.workload, seed=1))
     model = base["model"]
-
-    if args.rounds > 0 and args.batch > 0:
-        runs = [run_kwargs(run_params(args.workload, seed=1 + i)) for i in range(args.batch)]
-        b = rewl.Batch(runs, walkers_per_wave=args.walkers_per_wave, graph_rounds=args.graph)
-        if not args.graph:
-            b.set_timing(True)
-        b.step(1)
-        torch.cuda.synchronize()
-        a0 = sum(b[i].info()["attempts"] for i in range(len(b)))
-        t0 = time.perf_counter()
-        b.step(args.rounds)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ms, n = b.timing()
-        att = sum(b[i].info()["attempts"] for i in range(len(b))) - a0
-        log(f"profile: {args.batch} x {args.workload}, P={args.walkers_per_wave}, "
-            f"graph={args.graph}, {args.rounds} rounds, {att} attempts, {dt:.3f} s, "
-            f"{att / dt / 1e9:.3f} G attempts/s, sweep avg {1e3 * ms / max(n, 1):.1f} us")
-        b.close()
-        return
-    if args.rounds > 0:
-        r = rewl.Run(**run_kwargs(base))
-        r.set_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r.step(args.rounds)
-        ms, n = r.timing()
-        dt = time.perf_counter() - t0
-        att = r.info()["attempts"]
-        log(f"profile: {args.workload}, {args.rounds} rounds, {att} attempts, {dt:.3f} s, "
-            f"{att / dt / 1e9:.3f} G attempts/s, sweep avg {1e3 * ms / max(n, 1):.1f} us")
-        r.close()
-        return
-
     for i in range(args.warmup):
-        p = run_params(args.workload, seed=900 + i)
-        dt, att, rounds, _, _, ok = gpu_full_run(rewl, p, args.max_rounds)
-        log(f"warmup {i}: {dt:.2f} s, {rounds} rounds, converged={ok}")
+        res = gpu_full_run(rewl, run_params(args.workload, seed=900 + i), args.max_rounds)
+        log(f"warmup {i}: {res['seconds']:.2f} s, {res['rounds']} rounds")
 
-    times, attempts, rounds_l, sweep_ms, launches = [], 0, [], 0.0, 0
+    runs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        p = run_params(args.workload, seed=1 + i)
-        dt, att, rounds, ms, n, ok = gpu_full_run(rewl, p, args.max_rounds)
-        if not ok:
+        res = gpu_full_run(rewl, run_params(args.workload, seed=1 + i), args.max_rounds)
+        if not res["converged"]:
             log(f"step {i}: not converged within {args.max_rounds} rounds")
-        times.append(dt)
-        attempts += att
-        rounds_l.append(rounds)
-        sweep_ms += ms
-        launches += n
-        log(f"step {i}: {dt:.2f} s, {rounds} rounds, {att / dt / 1e9:.3f} G attempts/s")
+        runs.append(res)
+        log(f"step {i}: {res['seconds']:.2f} s, {res['rounds']} rounds, "
+            f"{res['attempts'] / res['seconds'] / 1e9:.3f} G attempts/s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    attempts = sum(r["attempts"] for r in runs)
+    sweep_ms = sum(r["sweep_ms"] for r in runs)
+    launches = sum(r["launches"] for r in runs)
+    times = [r["seconds"] for r in runs]
 
-    value = attempts / wall
     slots = VALU_SLOTS_PER_ATTEMPT[model]
     achieved = slots * attempts / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS if achieved else None, "traffic": None,
-                "kernel": f"sweep_kernel<{model}>",
+                "frac": achieved / VALU_PEAK_TOPS if achieved else None,
+                "traffic": profiled_traffic(args.workload),
+                "kernel": "sweep_kernel<1>",
                 "sweep_avg_us": 1e3 * sweep_ms / launches if launches else None,
                 "valu_slots_per_attempt": slots}
     out = {
         "metric": "spin-flip attempts/sec (1 GPU) + p50/p99 time-to-converged ln g, "
                   "batched vs plain",
-        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
+        "value": attempts / wall, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
@@ -211,17 +427,28 @@ def main():
                    "walkers": base["n_windows"] * base["walkers_per_window"],
                    "L": base["L"], "q": base["q"], "seeds": list(range(1, args.steps + 1))},
         "time_to_dos_s": {"p50": percentile(times, 50), "p99": percentile(times, 99),
-                          "rounds": rounds_l},
+                          "rounds": [r["rounds"] for r in runs]},
         "roofline": roofline,
     }
+    if args.batch > 0:
+        params = [run_params(args.workload, seed=1 + i) for i in range(args.batch)]
+        P = args.walkers_per_wave or autotune(rewl, params)
+        bres = gpu_batched(rewl, params, P, args.graph, args.max_rounds)
+        dts = [d for d in bres["done_at"] if d is not None]
+        out["batched"] = {"runs": args.batch, "walkers_per_wave": P, "graph_rounds": args.graph,
+                          "value": bres["attempts"] / bres["wall"], "unit": "attempts/s",
+                          "wall_s": bres["wall"], "converged": len(dts),
+                          "time_to_dos_s": {"p50": percentile(dts, 50),
+                                            "p99": percentile(dts, 99)},
+                          "seeds": list(range(1, args.batch + 1))}
+        log(f"batched: {args.batch} runs, P={P}, {bres['wall']:.1f} s, "
+            f"{bres['attempts'] / bres['wall'] / 1e9:.3f} G attempts/s")
     if not args.no_cpu:
         p = dict(run_params(args.workload, seed=1))
         p["name"] = args.workload
-        cb = cpu_baseline(p, args.cpu_seconds)
-        cb.pop("seconds_per_round")
-        # the oracle makes exactly the GPU's attempts (bit-identical runs)
-        cb["time_to_dos_s_extrapolated"] = (attempts / args.steps) / cb["value"]
-        out["cpu_baseline"] = cb
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else \
+            (os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, runs[0]["finish"], threads)
     print(json.dumps(out), flush=True)
 
 

@@ -54,6 +54,14 @@ enum {
 
 enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2 };
 
+/* ln f schedules.  REWL_HALVING: ln f halves at every merge (f -> sqrt f).
+ * REWL_ONE_OVER_T: halving until a halving would take ln f below W/t (W bins
+ * of the window, t attempts per walker so far); from then on ln f = W/t renewed
+ * after every attempt, the window's walkers are averaged every round without a
+ * flatness test, and the window is done once W/t < lnf_final (the 1/t rule of
+ * Belardinelli & Pereyra, one of the update rules the paper names as usable). */
+enum { REWL_HALVING = 0, REWL_ONE_OVER_T = 1 };
+
 /* Parameters of one run.
  *  couplings: REWL_EA only, 2*L*L values +-1, [2i] = J(i, right neighbour),
  *             [2i+1] = J(i, lower neighbour), site i = row*L + column; else NULL.
@@ -63,7 +71,7 @@ enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2 };
  *  n_windows >= 1, 0 < overlap < 1, walkers_per_window in [1, 64],
  *  0 < flatness <= 1, lnf_init > 0, lnf_final > 0,
  *  attempts_per_round >= 1 (attempts per walker between exchange steps),
- *  seed: Philox4x32-10 key.
+ *  seed: Philox4x32-10 key, schedule: REWL_HALVING or REWL_ONE_OVER_T.
  *  Windows narrower than 2 bins, overlaps below 2 bins, 3 > L or L > 256,
  *  q outside [2, 127] (Potts) are REWL_EINVAL. */
 typedef struct rewl_params {
@@ -81,6 +89,7 @@ typedef struct rewl_params {
     double lnf_final;
     int64_t attempts_per_round;
     uint64_t seed;
+    int schedule;  /* REWL_HALVING or REWL_ONE_OVER_T */
 } rewl_params;
 
 typedef struct rewl_ctx rewl_ctx; /* opaque, owned by the library */

@@ -15,6 +15,7 @@ SRC = os.path.join(HERE, "rewl_oracle.c")
 LIB = os.path.join(HERE, "librewl_oracle.so")
 
 MODELS = {"ising": 0, "potts": 1, "ea": 2}
+SCHEDULES = {"halving": 0, "1/t": 1}
 
 
 def build(force=False):
@@ -41,7 +42,7 @@ def lib():
         i64, u64, i32, u32, dbl = C.c_int64, C.c_uint64, C.c_int, C.c_uint32, C.c_double
         P = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(P), i32, i32, i32, P, i64, i64, i32, dbl, i32,
-                                 dbl, dbl, dbl, i64, u64, i32]
+                                 dbl, dbl, dbl, i64, u64, i32, i32]
         L.orc_destroy.argtypes = [P]
         L.orc_step.argtypes = [P, i64]
         L.orc_run_to.argtypes = [P, i64]
@@ -124,7 +125,7 @@ class Run:
 
     def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                  overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                 lnf_final=1e-6, S=10_000, seed=1, n_threads=1):
+                 lnf_final=1e-6, S=10_000, seed=1, n_threads=1, schedule="halving"):
         N = L * L
         if e_min is None:
             e_min = -2 * N
@@ -134,7 +135,7 @@ class Run:
         h = C.c_void_p()
         rc = lib().orc_create(C.byref(h), MODELS[model], L, q, _p(J), e_min, e_max, n_windows,
                               overlap, walkers_per_window, flatness, lnf_init, lnf_final, S,
-                              seed, n_threads)
+                              seed, n_threads, SCHEDULES[schedule])
         if rc:
             raise OracleError(rc, "orc_create")
         self._h = h

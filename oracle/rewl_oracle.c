@@ -26,6 +26,12 @@
  * reasons in the design notes of the repository):
  *  - ln f starts at lnf_init and halves at each merge (f -> sqrt f); a window is
  *    done when the halved ln f drops below lnf_final.
+ *  - optional 1/t schedule (Belardinelli & Pereyra, Phys. Rev. E 75, 046701
+ *    (2007), one of the update rules the paper names): once a halving would take
+ *    ln f below W/t (W bins of the window, t attempts per walker), the window
+ *    switches to ln f = W/t, renewed after every attempt; from then on its
+ *    walkers are averaged every round without a flatness test, and the window is
+ *    done when W/t drops below lnf_final.
  *  - flat: min H * n >= p * sum H over the walker's visited bins (visited is
  *    sticky over iterations and OR-ed at the merge).
  *  - windows: span = B-1, w = span/(1+(h-1)(1-o)), lo_k = floor(k(1-o)w),
@@ -200,12 +206,14 @@ struct orc_run {
     int64_t e_min, e_max, step, B, S, round;
     int full_lo, full_hi;   /* requested range reached the ground / top state */
     double p, lnf_final;
+    int schedule;       /* 0: halving, 1: halving then 1/t */
     uint64_t seed;
     int8_t *J;          /* 2N, EA only */
     int64_t *lo, *hi;   /* h windows, bins */
     int64_t Wmax;
     double *lnf;        /* h */
     int *done;          /* h */
+    int *phase;         /* h: 1 once the window runs the 1/t rule */
     int64_t *finish;    /* h: round in which the window finished, -1 before */
     int8_t *spins;      /* nw * N */
     int64_t *E;         /* nw */
@@ -231,7 +239,7 @@ static int in_window(const orc_run *run, int k, int64_t E)
 void orc_destroy(orc_run *run)
 {
     if (!run) return;
-    free(run->J); free(run->lo); free(run->hi); free(run->lnf); free(run->done);
+    free(run->J); free(run->lo); free(run->hi); free(run->lnf); free(run->done); free(run->phase);
     free(run->finish); free(run->spins); free(run->E); free(run->t); free(run->flat);
     free(run->lng); free(run->H); free(run->vis); free(run->n_acc);
     free(run);
@@ -290,13 +298,15 @@ static int init_walker(orc_run *run, int w)
 
 int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
                int64_t e_min, int64_t e_max, int h, double o, int m, double p,
-               double lnf_init, double lnf_final, int64_t S, uint64_t seed, int n_threads)
+               double lnf_init, double lnf_final, int64_t S, uint64_t seed, int n_threads,
+               int schedule)
 {
     *out = NULL;
     if (model < 0 || model > 2 || L < 3 || L > 256 || h < 1 || m < 1 || S < 1) return -1;
     if (model == ORC_POTTS && (q < 2 || q > 127)) return -1;
     if (model == ORC_EA && !couplings) return -1;
     if (!(p > 0.0 && p <= 1.0) || !(lnf_final > 0.0) || !(lnf_init > 0.0)) return -1;
+    if (schedule != 0 && schedule != 1) return -1;
     int N = L * L;
     int64_t step = (model == ORC_POTTS) ? 1 : 4;
     int64_t lo_full = -2 * (int64_t)N, hi_full = (model == ORC_POTTS) ? 0 : 2 * (int64_t)N;
@@ -328,7 +338,7 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->e_min = e_min; run->e_max = e_max; run->step = step;
     run->full_lo = full_lo; run->full_hi = full_hi;
     run->B = (e_max - e_min) / step + 1; run->S = S; run->p = p;
-    run->lnf_final = lnf_final; run->seed = seed;
+    run->lnf_final = lnf_final; run->seed = seed; run->schedule = schedule;
     run->lo = calloc(h, sizeof(int64_t)); run->hi = calloc(h, sizeof(int64_t));
     if (!run->lo || !run->hi) { orc_destroy(run); return -2; }
     if (orc_partition(run->B, h, o, run->lo, run->hi)) { orc_destroy(run); return -1; }
@@ -337,6 +347,7 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     size_t nw = (size_t)run->nw;
     run->J = calloc(2 * (size_t)N, 1);
     run->lnf = calloc(h, sizeof(double)); run->done = calloc(h, sizeof(int));
+    run->phase = calloc(h, sizeof(int));
     run->finish = calloc(h, sizeof(int64_t));
     run->spins = calloc(nw * N, 1); run->E = calloc(nw, sizeof(int64_t));
     run->t = calloc(nw, sizeof(uint64_t)); run->flat = calloc(nw, sizeof(int));
@@ -344,7 +355,7 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->H = calloc(nw * run->Wmax, sizeof(uint32_t));
     run->vis = calloc(nw * run->Wmax, 1);
     run->n_acc = calloc(nw, sizeof(uint64_t));
-    if (!run->J || !run->lnf || !run->done || !run->finish || !run->spins || !run->E ||
+    if (!run->J || !run->lnf || !run->done || !run->phase || !run->finish || !run->spins || !run->E ||
         !run->t || !run->flat || !run->lng || !run->H || !run->vis || !run->n_acc) {
         orc_destroy(run);
         return -2;
@@ -371,6 +382,8 @@ static void sweep_walker(orc_run *run, int w)
     uint32_t *H = run->H + (size_t)w * run->Wmax;
     uint8_t *vis = run->vis + (size_t)w * run->Wmax;
     double lnf = run->lnf[k];
+    int one_over_t = run->phase[k];
+    double Wd = (double)wsize(run, k);
     int64_t lo = run->lo[k];
     int64_t E = run->E[w];
     uint64_t acc = 0;
@@ -393,6 +406,7 @@ static void sweep_walker(orc_run *run, int w)
             }
         }
         int64_t b = bin_of(run, E) - lo;
+        if (one_over_t) lnf = Wd / (double)run->t[w]; /* W / attempts made so far */
         lng[b] = lng[b] + lnf;
         H[b] += 1;
         vis[b] = 1;
@@ -441,7 +455,16 @@ static void merge_window(orc_run *run, int k, int64_t round)
         }
     }
     for (int s = 0; s < m; ++s) run->flat[k * m + s] = 0;
-    run->lnf[k] = run->lnf[k] * 0.5;
+    double Wt = (double)W / (double)run->t[k * m]; /* the window's walkers share t */
+    if (run->phase[k]) {
+        run->lnf[k] = Wt;
+    } else {
+        run->lnf[k] = run->lnf[k] * 0.5;
+        if (run->schedule == 1 && run->lnf[k] < Wt) {
+            run->phase[k] = 1;
+            run->lnf[k] = Wt;
+        }
+    }
     if (run->lnf[k] < run->lnf_final) {
         run->done[k] = 1;
         run->finish[k] = round;
@@ -529,12 +552,13 @@ static void one_round(orc_run *run)
     for (int w = 0; w < run->nw; ++w)
         if (!run->done[window_of(run, w)]) sweep_walker(run, w);
     for (int w = 0; w < run->nw; ++w)
-        if (!run->done[window_of(run, w)] && !run->flat[w]) run->flat[w] = is_flat(run, w);
+        if (!run->done[window_of(run, w)] && !run->phase[window_of(run, w)] && !run->flat[w])
+            run->flat[w] = is_flat(run, w);
     for (int k = 0; k < run->h; ++k) {
         if (run->done[k]) continue;
         int all = 1;
         for (int s = 0; s < run->m; ++s) all &= run->flat[k * run->m + s];
-        if (all) merge_window(run, k, r);
+        if (all || run->phase[k]) merge_window(run, k, r);
     }
     exchange(run, r);
     run->round += 1;

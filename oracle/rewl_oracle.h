@@ -28,11 +28,12 @@ typedef struct orc_run orc_run;
  * copied.  e_min/e_max are inclusive; for EA they are aligned inwards onto the
  * energy class of the couplings.  lnf_init is the first ln f; S the number of
  * attempts per walker per round; n_threads the OpenMP threads used by the
- * sweep (0 = runtime default). */
+ * sweep (0 = runtime default); schedule 0 halves ln f at every merge, 1 halves
+ * it until it would drop below W/t and then follows W/t (the 1/t rule). */
 int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
                int64_t e_min, int64_t e_max, int n_windows, double overlap,
                int walkers_per_window, double flatness, double lnf_init,
-               double lnf_final, int64_t S, uint64_t seed, int n_threads);
+               double lnf_final, int64_t S, uint64_t seed, int n_threads, int schedule);
 void orc_destroy(orc_run *run);
 
 /* Advance exactly `rounds` rounds (rounds of a finished run change nothing). */

@@ -33,7 +33,10 @@ class Params(C.Structure):
                 ("n_windows", C.c_int), ("overlap", C.c_double),
                 ("walkers_per_window", C.c_int), ("flatness", C.c_double),
                 ("lnf_init", C.c_double), ("lnf_final", C.c_double),
-                ("attempts_per_round", C.c_int64), ("seed", C.c_uint64)]
+                ("attempts_per_round", C.c_int64), ("seed", C.c_uint64),
+                ("schedule", C.c_int)]
+
+SCHEDULES = {"halving": 0, "1/t": 1}
 
 
 _lib = None
@@ -102,7 +105,7 @@ def _p(a):
 
 def make_params(model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                 overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                lnf_final=1e-6, S=10_000, seed=1):
+                lnf_final=1e-6, S=10_000, seed=1, schedule="halving"):
     N = L * L
     if e_min is None:
         e_min = -2 * N
@@ -111,7 +114,7 @@ def make_params(model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows
     J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
     p = Params(MODELS[model], L, q, None if J is None else J.ctypes.data, int(e_min),
                int(e_max), n_windows, overlap, walkers_per_window, flatness, lnf_init,
-               lnf_final, int(S), int(seed))
+               lnf_final, int(S), int(seed), SCHEDULES[schedule])
     return p, J
 
 
@@ -188,13 +191,13 @@ class Run(RunView):
 
     def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                  overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                 lnf_final=1e-6, S=10_000, seed=1, stream=None):
+                 lnf_final=1e-6, S=10_000, seed=1, schedule="halving", stream=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
         p, J = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
-                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed)
+                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed, schedule)
         dev, lds = C.c_size_t(), C.c_size_t()
         _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
         self._buf = torch.empty(dev.value, dtype=torch.uint8, device="cuda")
@@ -206,7 +209,8 @@ class Run(RunView):
         self._attach(h, model, L, dict(model=model, L=L, q=q, n_windows=n_windows,
                                        overlap=overlap, walkers_per_window=walkers_per_window,
                                        flatness=flatness, lnf_init=lnf_init,
-                                       lnf_final=lnf_final, S=S, seed=seed))
+                                       lnf_final=lnf_final, S=S, seed=seed,
+                                       schedule=schedule))
 
     def close(self):
         h = getattr(self, "_h", None)

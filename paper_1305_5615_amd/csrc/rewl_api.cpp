@@ -90,6 +90,8 @@ int validate(const rewl_params *p, Geometry &g)
     if (!(p->lnf_init > 0.0) || !(p->lnf_final > 0.0))
         return fail(REWL_EINVAL, "lnf_init and lnf_final must be > 0");
     if (p->attempts_per_round < 1) return fail(REWL_EINVAL, "attempts_per_round must be >= 1");
+    if (p->schedule != REWL_HALVING && p->schedule != REWL_ONE_OVER_T)
+        return fail(REWL_EINVAL, "unknown ln f schedule");
     const int64_t N = (int64_t)p->L * p->L;
     g.N = (int)N;
     g.step = (p->model == REWL_POTTS) ? 1 : 4;
@@ -135,8 +137,8 @@ int validate(const rewl_params *p, Geometry &g)
 
 // Byte offsets of the arrays inside the device allocation.
 struct Layout {
-    size_t spins, E, t, flat, lng, H, n_acc, lnf, done, finish, lo, hi, ex_prop, ex_acc, J4,
-        round, status, total;
+    size_t spins, E, t, flat, lng, H, n_acc, lnf, done, phase, finish, lo, hi, ex_prop, ex_acc,
+        J4, round, status, total;
 };
 
 Layout layout(const rewl_params *p, const Geometry &g)
@@ -158,6 +160,7 @@ Layout layout(const rewl_params *p, const Geometry &g)
     l.n_acc = take(nw * 8);
     l.lnf = take(h * 8);
     l.done = take(h * 4);
+    l.phase = take(h * 4);
     l.finish = take(h * 8);
     l.lo = take(h * 4);
     l.hi = take(h * 4);
@@ -514,6 +517,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     d.key0 = (uint32_t)p->seed;
     d.key1 = (uint32_t)(p->seed >> 32);
     d.S = p->attempts_per_round;
+    d.schedule = p->schedule;
     d.flat_p = p->flatness;
     d.lnf_final = p->lnf_final;
     d.spins = (int8_t *)(b + h->l.spins);
@@ -525,6 +529,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     d.n_acc = (unsigned long long *)(b + h->l.n_acc);
     d.lnf = (double *)(b + h->l.lnf);
     d.done = (int *)(b + h->l.done);
+    d.phase = (int *)(b + h->l.phase);
     d.finish = (long long *)(b + h->l.finish);
     d.lo = (int *)(b + h->l.lo);
     d.hi = (int *)(b + h->l.hi);
@@ -722,6 +727,7 @@ int rewl_create(rewl_ctx **out, int model, int L, int q, const int8_t *couplings
     p.lnf_final = lnf_final;
     p.attempts_per_round = 10000;
     p.seed = seed;
+    p.schedule = REWL_HALVING;
     return rewl_create_ex(out, &p, nullptr, 0, nullptr);
 }
 

@@ -8,7 +8,8 @@
 //   lng     nw x Wmax f64    (window-local ln g; visited <=> lng > 0)
 //   H       nw x Wmax uint32 (window-local histogram of the current iteration)
 //   n_acc   nw uint64        (accepted sweep moves)
-//   lnf     h f64, done h int32, finish h int64, lo/hi h int32 (bins)
+//   lnf     h f64, done h int32, phase h int32 (1/t rule active), finish h
+//           int64, lo/hi h int32 (bins)
 //   ex_prop, ex_acc  h uint64 (exchange proposals / acceptances of pair (k,k+1))
 //   J4      N uint32         (EA: couplings to right, left, down, up neighbour,
 //                             one int8 each, packed little-endian)
@@ -29,6 +30,7 @@ struct RunDesc {
     uint32_t l_magic;  // ceil(2^32 / L): row = mulhi(site, l_magic) for site < L*L
     uint32_t key0, key1;
     long long S;
+    int schedule;      // 0 halving, 1 halving then 1/t
     double flat_p, lnf_final;
     int8_t *spins;
     int *E;
@@ -39,6 +41,7 @@ struct RunDesc {
     unsigned long long *n_acc;
     double *lnf;
     int *done;
+    int *phase;        // per window: 1 once it follows the 1/t rule
     long long *finish;
     int *lo, *hi;
     unsigned long long *ex_prop, *ex_acc;
@@ -74,14 +77,14 @@ struct BatchDev {
 constexpr int kWave = 64;
 struct alignas(16) Prop {
     double thr;        // ln u of the attempt
-    int32_t d_off;     // energy change against the block-start configuration
-    int32_t d_addr;    // the same change in bytes of the per-bin LDS records
+    double lnf;        // ln f added after the attempt
+    int32_t d_addr;    // energy change against the block-start configuration,
+                       // in bytes of the LDS ln g array
     uint32_t sp_off;   // LDS byte offset of the site's spin
     uint32_t flags;    // new state (8 bits) | old state << 8 | Potts r1 << 16
                        // | 1 << 31 if an earlier proposal of the block touches
                        //   the site or one of its neighbours
     uint32_t site;
-    uint32_t pad;
 };
 
 // LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:

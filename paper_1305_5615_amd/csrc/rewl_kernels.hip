@@ -10,7 +10,8 @@
 //                      of the standard WL walk (standard-WL paragraph);
 //   flat_merge_kernel  one work-group per window: flatness of each walker,
 //                      and when all m are flat the mean of their ln g, H reset,
-//                      ln f halved (parallel-scheme paragraph);
+//                      ln f halved (parallel-scheme paragraph); under the 1/t
+//                      rule ln f = W/t and the merge runs every round;
 //   exchange_kernel    one work-group per window pair (k, k+1), k = round mod
 //                      2: partner permutation, Eq. (1) test, configuration swap;
 //   advance_kernel     each run's round counter + 1.
@@ -273,13 +274,16 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
         for (int i = gl; i < N; i += G) tag[i] = (TagT)0;
     }
-    if (gl < 2) stage[G + gl] = Prop{0.0, 0, 0, sp_base, 0u, 0u, 0u};
+    if (gl < 2) stage[G + gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
     if (MODEL == kEA)
         for (int i = lane; i < N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
 
     const int elo = a.e_min + lo * STEP;
     const double lnf = live ? a.lnf[k] : 0.0;
+    // the 1/t rule: ln f = W / t after each attempt, t = attempts made so far
+    const bool one_over_t = live && a.phase[k] != 0;
+    const double Wd = (double)W;
     const unsigned long long t0 = live ? a.t[w] : 0ull;
     const long long S = a.S;
     // chain state, identical in every lane of the group: LDS byte offset of
@@ -326,17 +330,16 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                                   tag[cur.up];
             Prop p;
             p.thr = cur.thr;
-            p.d_off = dE;
+            p.lnf = one_over_t ? Wd / (double)(t0 + (unsigned long long)base + gl + 1) : lnf;
             p.d_addr = dE * ADDR_PER_E;
             p.sp_off = sp_base + (uint32_t)cur.site;
             p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (cur.r1 << 16) |
                       ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
             p.site = (uint32_t)cur.site;
-            p.pad = 0;
             stage[gl] = p;
         } else {
             // records past the last attempt: a zero move, read ahead only
-            stage[gl] = Prop{0.0, 0, 0, sp_base, 0u, 0u, 0u};
+            stage[gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
         }
         __syncthreads();
         if (active) tag[cur.site] = (TagT)0;
@@ -350,19 +353,19 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             // record is loaded before the previous attempt's LDS stores, which
             // the compiler may not move loads across.
             struct Fast {
-                double thr;
-                int d_off, d_addr;
+                double thr, lnf;
+                int d_addr;
                 uint32_t sp_off, flags;
             };
             auto fetch = [&](int j) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(&stage[j]);
-                const uint2 u = *reinterpret_cast<const uint2 *>(&stage[j].sp_off);
+                const uint4 u = *reinterpret_cast<const uint4 *>(&stage[j].d_addr);
                 Fast f;
                 f.thr = __hiloint2double((int)v.y, (int)v.x);
-                f.d_off = (int)v.z;
-                f.d_addr = (int)v.w;
-                f.sp_off = u.x;
-                f.flags = u.y;
+                f.lnf = __hiloint2double((int)v.w, (int)v.z);
+                f.d_addr = (int)u.x;
+                f.sp_off = u.y;
+                f.flags = u.z;
                 return f;
             };
             auto attempt = [&](const Fast &p, int j) {
@@ -386,7 +389,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 baddr = accept ? naddr : baddr;
                 gcur = accept ? gn : gcur;
                 acc += accept ? 1u : 0u;
-                gcur = gcur + lnf;
+                gcur = gcur + p.lnf;
                 *reinterpret_cast<double *>(smem + baddr) = gcur;
                 hb = (gl == j) ? baddr : hb;
             };
@@ -457,7 +460,8 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
     __shared__ unsigned int sh_min[4], sh_n[4];
     __shared__ int sh_all;
     const int tid = threadIdx.x, wave = tid >> 6;
-    for (int s = 0; s < m; ++s) {
+    const bool one_over_t = a.phase[k] != 0;  // no flatness test: merge every round
+    for (int s = 0; s < m && !one_over_t; ++s) {
         const int w = k * m + s;
         if (a.flat[w]) continue;
         const double *g = a.lng + (size_t)w * a.Wmax;
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
     if (tid == 0) {
         int all = 1;
         for (int s = 0; s < m; ++s) all &= (a.flat[k * m + s] != 0);
-        sh_all = all;
+        sh_all = all || one_over_t;
     }
     __syncthreads();
     if (!sh_all) return;
@@ -515,7 +519,17 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
     }
     if (tid == 0) {
         for (int s = 0; s < m; ++s) a.flat[k * m + s] = 0;
-        const double nl = a.lnf[k] * 0.5;
+        const double Wt = (double)W / (double)a.t[k * m];  // the window's walkers share t
+        double nl;
+        if (one_over_t) {
+            nl = Wt;
+        } else {
+            nl = a.lnf[k] * 0.5;
+            if (a.schedule == 1 && nl < Wt) {
+                a.phase[k] = 1;
+                nl = Wt;
+            }
+        }
         a.lnf[k] = nl;
         if (nl < a.lnf_final) {
             a.done[k] = 1;

@@ -111,6 +111,38 @@ def test_rounds_bitexact(gpu, orc, name, kw):
         assert_same_state(g, o, f"{name} after {done_rounds} rounds")
 
 
+ONE_OVER_T = [
+    # name, parameters, round increments: the checkpoints fall before, across
+    # and after each window's switch from halving to the 1/t rule, and after
+    # the windows finish
+    ("ising6_1t", dict(model="ising", L=6, n_windows=3, walkers_per_window=2, S=300,
+                       flatness=0.6, lnf_final=2e-4, seed=9), (1, 270, 20, 30, 100)),
+    ("ea6_1t", dict(model="ea", L=6, n_windows=3, walkers_per_window=3, S=129, flatness=0.6,
+                    lnf_final=1e-4, seed=10), (1, 900, 400, 700, 100)),
+    ("potts5q3_1t", dict(model="potts", L=5, q=3, n_windows=2, walkers_per_window=2, S=200,
+                         flatness=0.6, lnf_final=1e-4, seed=11), (1, 530, 170, 1400)),
+]
+
+
+@pytest.mark.parametrize("name,kw,steps", ONE_OVER_T, ids=[c[0] for c in ONE_OVER_T])
+def test_one_over_t_rounds_bitexact(gpu, orc, name, kw, steps):
+    kw = dict(kw, schedule="1/t")
+    if kw["model"] == "ea":
+        kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+    g, o = _pair(gpu, orc, **kw)
+    done_rounds = 0
+    for rounds in steps:
+        g.step(rounds)
+        o.step(rounds)
+        done_rounds += rounds
+        assert_same_state(g, o, f"{name} after {done_rounds} rounds")
+    assert o.info()["done"]
+    lg, lo = g.lng(), o.lng()
+    fin = np.isfinite(lo)
+    assert np.array_equal(np.isfinite(lg), fin)
+    assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
+
+
 def test_ising8_full_run_bitexact(gpu, orc):
     """The small Ising workload run to convergence: same rounds, same stitched ln g."""
     p = run_params("ising8", seed=2)

@@ -405,6 +405,66 @@ def test_merge_and_schedule(oracle_lib):
         assert w["done"] and w["lnf"] < 1e-3 <= 2 * w["lnf"]
 
 
+def test_one_over_t_schedule(oracle_lib):
+    """1/t rule: ln f halves until a halving would drop below W/t; from then on
+    ln f = W/t exactly (W window bins, t attempts per walker), the walkers of
+    the window are averaged every round, and the window ends once W/t is below
+    the final ln f."""
+    S, final = 5000, 1e-6
+    run = oracle_lib.Run("ising", 6, n_windows=2, walkers_per_window=2, S=S, seed=4,
+                         lnf_final=final, schedule="1/t")
+    prev = [1.0, 1.0]
+    switched = [None, None]
+    ended = [False, False]
+    for _ in range(10_000):
+        run.step(1)
+        for k in range(2):
+            if ended[k]:
+                continue
+            win = run.window(k)
+            W = win["hi"] - win["lo"] + 1
+            sts = [run.walker(2 * k + s) for s in range(2)]
+            t = sts[0]["t"]
+            assert sts[1]["t"] == t
+            if switched[k] is not None:
+                assert win["lnf"] == W / t
+                assert np.array_equal(sts[0]["lng"], sts[1]["lng"])
+            elif win["lnf"] != prev[k]:
+                if win["lnf"] == prev[k] * 0.5:
+                    assert prev[k] * 0.5 >= W / t
+                else:
+                    assert win["lnf"] == W / t and prev[k] * 0.5 < W / t
+                    switched[k] = t
+            prev[k] = win["lnf"]
+            ended[k] = win["done"]
+            if win["done"]:
+                assert win["lnf"] < final
+                if switched[k] is not None:   # ended on the first W/t below final
+                    assert final <= W / (t - S)
+        if run.info()["done"]:
+            break
+    assert run.info()["done"]
+    assert all(x is not None for x in switched), switched
+
+
+def test_one_over_t_removes_saturation(oracle_lib):
+    """6x6 Ising against the exact DOS: halving to ln f = 1e-6 stalls at errors
+    of 0.1-0.2, the 1/t rule reaches a few hundredths by ln f = 1e-5."""
+    _E, ref = None, None
+    from oracle import exact
+
+    ref = np.array([math.log(n) if n > 0 else -np.inf for n in exact.ising_dos_exact(6)])
+    errs = {"halving": [], "1/t": []}
+    for sched, lf in (("halving", 1e-6), ("1/t", 1e-5)):
+        for seed in (1, 2, 3):
+            run = oracle_lib.Run("ising", 6, n_windows=4, walkers_per_window=2, lnf_final=lf,
+                                 S=10_000, seed=seed, schedule=sched)
+            assert run.run()
+            errs[sched].append(_max_err(run.lng(), ref))
+    assert max(errs["1/t"]) < 0.08, errs
+    assert np.mean(errs["1/t"]) < 0.5 * np.mean(errs["halving"]), errs
+
+
 def test_histogram_counts_attempts(oracle_lib):
     run = oracle_lib.Run("potts", 5, q=3, n_windows=3, walkers_per_window=2, S=777, seed=8)
     run.step(1)

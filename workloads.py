@@ -55,13 +55,22 @@ def run_params(name, seed=1, **over):
     return p
 
 
-def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6)):
+SERVED_SIZES = {
+    # Ising L choices, Potts L range, +-J L range, windows range (inclusive)
+    "full": ((16, 24, 32, 48, 64), (16, 48), (16, 32), (4, 32)),
+    "small": ((8, 12, 16), (8, 16), (8, 16), (4, 16)),
+}
+
+
+def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6), sizes="full"):
     """Poisson arrivals of REWL requests with a mix of models and sizes.
 
-    Ising L in {16,24,32,48,64}; Potts q in 2..10, L in 16..48; +-J L in 16..32;
-    windows 4..32; walkers 2, 4 or 8 per window.  Returns a list of dicts with an
-    'arrival' time in seconds and the run parameters.
+    sizes="full": Ising L in {16,24,32,48,64}; Potts q in 2..10, L in 16..48;
+    +-J L in 16..32; windows 4..32.  sizes="small": the same mix on L <= 16 and
+    4..16 windows, for runs of seconds.  Walkers 2, 4 or 8 per window.  Returns
+    a list of dicts with an 'arrival' time in seconds and the run parameters.
     """
+    ising_L, potts_L, ea_L, hs = SERVED_SIZES[sizes]
     rng = np.random.default_rng(np.random.SeedSequence([0x5E, int(seed)]))
     t = 0.0
     out = []
@@ -69,15 +78,15 @@ def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6)
         t += rng.exponential(1.0 / rate_per_s)
         kind = ("ising", "potts", "ea")[rng.integers(3)]
         if kind == "ising":
-            L = int(rng.choice([16, 24, 32, 48, 64]))
+            L = int(rng.choice(list(ising_L)))
             q = 2
         elif kind == "potts":
-            L = int(rng.integers(16, 49))
+            L = int(rng.integers(potts_L[0], potts_L[1] + 1))
             q = int(rng.integers(2, 11))
         else:
-            L = int(rng.integers(16, 33))
+            L = int(rng.integers(ea_L[0], ea_L[1] + 1))
             q = 2
-        h = int(rng.integers(4, 33))
+        h = int(rng.integers(hs[0], hs[1] + 1))
         m = int(rng.choice([2, 4, 8]))
         e_min, e_max = full_range(kind, L)
         p = dict(model=kind, L=L, q=q, n_windows=h, overlap=0.75, walkers_per_window=m,
