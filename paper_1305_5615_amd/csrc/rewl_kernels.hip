@@ -222,6 +222,20 @@ __device__ __forceinline__ void tag_set(typename TagOf<G>::T *tag, int site, uin
     }
 }
 
+// bit 0 of every group of G lanes in a 64-bit lane mask
+template <int G> struct kFirstLanes {
+    static constexpr uint64_t value = (G == 64) ? 1ull : (kFirstLanes<2 * G>::value * ((1ull << G) + 1ull));
+};
+template <> struct kFirstLanes<64> { static constexpr uint64_t value = 1ull; };
+
+// sum over the G aligned lanes of a walker group
+template <int G>
+__device__ __forceinline__ unsigned int group_sum(unsigned int v)
+{
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // guard bins on either side of a window's ln g: the largest single-site
 // energy change is 8 (Ising, +-J: 2 bins of 4) or 4 (Potts: 4 bins of 1)
 constexpr int kGuard = 4;
@@ -345,13 +359,15 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         if (active) tag[cur.site] = (TagT)0;
         // draws of the next block do not depend on the walk and overlap with it
         const Draw nxt_draw = draw(base + G);
-        uint32_t hb = baddr;  // bin this lane's attempt ends in (for H)
+        // flagged attempts of the block, one bit per lane (wave-uniform)
+        const uint64_t fmask = __builtin_amdgcn_ballot_w64(active && (stage[gl].flags >> 31));
         if (live) {
-            // In-order pass, executed identically by every lane of the group;
-            // branch-free except for flagged attempts.  The candidate bin is
-            // clamped into the window so its ln g can always be loaded; each
-            // record is loaded before the previous attempt's LDS stores, which
-            // the compiler may not move loads across.
+            // In-order pass, executed identically by every lane of the group.
+            // The only branch is taken when some group of the wave has a
+            // flagged attempt at this position; it is wave-uniform (a scalar
+            // test of the ballot), so unflagged positions cost no exec-mask
+            // changes.  Each record is loaded before the previous attempt's
+            // LDS stores, which the compiler may not move loads across.
             struct Fast {
                 double thr, lnf;
                 int d_addr;
@@ -372,13 +388,19 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 int d_addr = p.d_addr;
                 int nw = (int)(int8_t)(p.flags & 0xFFu);
                 int old = (int)(int8_t)((p.flags >> 8) & 0xFFu);
-                if (p.flags & 0x80000000u) {
+                if (fmask & (kFirstLanes<G>::value << j)) {
+                    // some group's attempt j is flagged: every group recomputes
+                    // from its current spins, the flagged ones keep the result
                     const int s = (int)stage[j].site;
                     const Nbrs nb = neighbours(s, L, N, a.l_magic);
-                    old = sp[s];
-                    nw = new_state<MODEL>(old, (p.flags >> 16) & 0x7Fu, q);
-                    d_addr = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, old, nw) *
-                             ADDR_PER_E;
+                    const int o2 = sp[s];
+                    const int n2 = new_state<MODEL>(o2, (p.flags >> 16) & 0x7Fu, q);
+                    const int d2 = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, o2, n2) *
+                                   ADDR_PER_E;
+                    const bool f = (p.flags & 0x80000000u) != 0;
+                    old = f ? o2 : old;
+                    nw = f ? n2 : nw;
+                    d_addr = f ? d2 : d_addr;
                 }
                 // outside the window the target holds +inf: gcur - gn = -inf
                 // never exceeds ln u, so the move is rejected
@@ -388,10 +410,10 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 smem[p.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
                 baddr = accept ? naddr : baddr;
                 gcur = accept ? gn : gcur;
-                acc += accept ? 1u : 0u;
                 gcur = gcur + p.lnf;
                 *reinterpret_cast<double *>(smem + baddr) = gcur;
-                hb = (gl == j) ? baddr : hb;
+                // bin after attempt j and its acceptance, for lane j's H update
+                stage[j].site = baddr | (accept ? 1u : 0u);
             };
             Fast f = fetch(0);
             if (n == G) {
@@ -410,7 +432,11 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             }
         }
         // H of the block's attempts, one atomic per lane
-        if (active) atomicAdd(&H_s[(hb - lng_base) >> 3], 1u);
+        if (active) {
+            const uint32_t v = stage[gl].site;
+            atomicAdd(&H_s[((v & ~7u) - lng_base) >> 3], 1u);
+            acc += v & 1u;
+        }
         cur = nxt_draw;
         __syncthreads();
     }
@@ -423,10 +449,11 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
         uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
+        const unsigned int acc_w = group_sum<G>(acc);
         if (gl == 0) {
             a.E[w] = elo + (int)((baddr - lng_base) >> 3) * STEP;
             a.t[w] = t0 + (unsigned long long)S;
-            a.n_acc[w] += acc;
+            a.n_acc[w] += acc_w;
         }
     }
 }
