@@ -13,6 +13,11 @@ Reported on one JSON line:
   batched       the same workload, `--batch` seeds at once in one batch
                 (walkers per wave chosen by the autotuner): aggregate
                 attempts/s and per-run time-to-DOS p50 / p99;
+  max_abs_dlng_vs_exact  per step, max |ln g - ln g_exact| over the bins
+                (Ising sizes with a stored exact DOS);
+  batched_glasses  256 independent 24x24 +-J glasses, 8 windows x 4 walkers
+                each, in one batch for a fixed number of rounds: attempts/s and
+                the sweep kernel's roofline (same definition as below);
   roofline      the sweep kernel's VALU work per attempt times its attempts,
                 over its own time measured with HIP events recorded on the run's
                 stream around each sweep launch, against the MI355X vector-ALU
@@ -129,7 +134,60 @@ def gpu_full_run(rewl, p, max_rounds):
     r.close()
     assert lng.shape[0] == info["n_bins"]
     return dict(seconds=t1 - t0, attempts=info["attempts"], rounds=rounds, sweep_ms=ms,
-                launches=n, converged=ok, finish=finish)
+                launches=n, converged=ok, finish=finish, lng=lng)
+
+
+def exact_error(p, lng):
+    """max |ln g - ln g_exact| over the bins of an Ising run whose exact DOS is
+    stored under tests/golden (None for other models and sizes)."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", f"ising_exact_L{p['L']}.txt")
+    if p["model"] != "ising" or not os.path.exists(path):
+        return None
+    ref = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            v = line.split()[1]
+            if p["L"] <= 16:
+                n = int(v)
+                ref.append(math.log(n) if n > 0 else -math.inf)
+            else:
+                ref.append(float(v))
+    ref = np.array(ref)
+    fin = np.isfinite(ref)
+    if not np.array_equal(np.isfinite(lng), fin):
+        return float("inf")
+    return float(np.abs(lng[fin] - ref[fin]).max())
+
+
+def gpu_glasses(rewl, n_runs, rounds, candidates=(4, 8)):
+    """The batched glass workload: n_runs independent 24x24 +-J instances in one
+    batch, a fixed number of rounds after start-up, walkers per wave tuned over
+    `candidates`.  Returns throughput and the sweep kernel's own time."""
+    import torch
+
+    from workloads import run_params
+
+    runs = [run_kwargs(run_params("ea24", seed=1 + i)) for i in range(n_runs)]
+    P = autotune(rewl, [run_params("ea24", seed=1 + i) for i in range(n_runs)], candidates,
+                 rounds=4)
+    b = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
+    b.set_timing(True)
+    b.step(1)
+    torch.cuda.synchronize()
+    a0 = sum(b[i].info()["attempts"] for i in range(n_runs))
+    ms0, n0 = b.timing()
+    t0 = time.perf_counter()
+    b.step(rounds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = b.timing()
+    att = sum(b[i].info()["attempts"] for i in range(n_runs)) - a0
+    b.close()
+    return dict(P=P, attempts=att, wall=wall, sweep_ms=ms - ms0, launches=n - n0)
 
 
 def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
@@ -352,6 +410,10 @@ def main():
     ap.add_argument("--walkers-per-wave", type=int, default=0,
                     help="batched form: walkers per wave (0: autotune)")
     ap.add_argument("--graph", type=int, default=16, help="batched form: rounds per graph")
+    ap.add_argument("--glasses", type=int, default=256,
+                    help="batched glass leg: independent 24x24 +-J runs in one batch (0: skip)")
+    ap.add_argument("--glass-rounds", type=int, default=100,
+                    help="batched glass leg: rounds timed after start-up")
     ap.add_argument("--rounds", type=int, default=0,
                     help="profile mode: run this many rounds after start-up, then exit")
     ap.add_argument("--served", type=int, default=0,
@@ -428,6 +490,7 @@ def main():
                    "L": base["L"], "q": base["q"], "seeds": list(range(1, args.steps + 1))},
         "time_to_dos_s": {"p50": percentile(times, 50), "p99": percentile(times, 99),
                           "rounds": [r["rounds"] for r in runs]},
+        "max_abs_dlng_vs_exact": [exact_error(base, r["lng"]) for r in runs],
         "roofline": roofline,
     }
     if args.batch > 0:
@@ -443,6 +506,23 @@ def main():
                           "seeds": list(range(1, args.batch + 1))}
         log(f"batched: {args.batch} runs, P={P}, {bres['wall']:.1f} s, "
             f"{bres['attempts'] / bres['wall'] / 1e9:.3f} G attempts/s")
+    if args.glasses > 0:
+        g = gpu_glasses(rewl, args.glasses, args.glass_rounds)
+        ach = VALU_SLOTS_PER_ATTEMPT["ea"] * g["attempts"] / (g["sweep_ms"] * 1e-3) / 1e12
+        out["batched_glasses"] = {
+            "workload": f"{args.glasses} independent 2D +-J EA glasses L=24, 8 windows x 4 "
+                        f"walkers each, {args.glass_rounds} rounds of 1e4 attempts/walker, "
+                        "one batch",
+            "walkers_per_wave": g["P"], "value": g["attempts"] / g["wall"],
+            "unit": "attempts/s",
+            "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                         "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
+                         "traffic": profiled_traffic(f"ea24x{args.glasses}_P{g['P']}"),
+                         "kernel": f"sweep_kernel<{g['P']}>",
+                         "sweep_avg_us": 1e3 * g["sweep_ms"] / max(g["launches"], 1),
+                         "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT["ea"]}}
+        log(f"glasses: {args.glasses} runs, P={g['P']}, "
+            f"{g['attempts'] / g['wall'] / 1e9:.2f} G attempts/s")
     if not args.no_cpu:
         p = dict(run_params(args.workload, seed=1))
         p["name"] = args.workload
