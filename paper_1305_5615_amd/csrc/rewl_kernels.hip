@@ -228,6 +228,8 @@ template <int G> struct kFirstLanes {
 };
 template <> struct kFirstLanes<64> { static constexpr uint64_t value = 1ull; };
 
+__device__ __forceinline__ double pick(bool c, double a, double b) { return c ? a : b; }
+
 // sum over the G aligned lanes of a walker group
 template <int G>
 __device__ __forceinline__ unsigned int group_sum(unsigned int v)
@@ -288,7 +290,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
         for (int i = gl; i < N; i += G) tag[i] = (TagT)0;
     }
-    if (gl < 2) stage[G + gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
+    for (int i = gl; i < 2; i += G) stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
     if (MODEL == kEA)
         for (int i = lane; i < N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
@@ -366,69 +368,74 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             // The only branch is taken when some group of the wave has a
             // flagged attempt at this position; it is wave-uniform (a scalar
             // test of the ballot), so unflagged positions cost no exec-mask
-            // changes.  Each record is loaded before the previous attempt's
-            // LDS stores, which the compiler may not move loads across.
-            struct Fast {
+            // changes.  As soon as an attempt is decided, the ln g at the next
+            // attempt's target is loaded, ahead of the current bin's write-back
+            // (so the LDS round trip overlaps that work), and the written
+            // value is forwarded when the next target is the current bin.
+            struct Rec {
                 double thr, lnf;
-                int d_addr;
+                int d;
                 uint32_t sp_off, flags;
             };
             auto fetch = [&](int j) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(&stage[j]);
                 const uint4 u = *reinterpret_cast<const uint4 *>(&stage[j].d_addr);
-                Fast f;
+                Rec f;
                 f.thr = __hiloint2double((int)v.y, (int)v.x);
                 f.lnf = __hiloint2double((int)v.w, (int)v.z);
-                f.d_addr = (int)u.x;
+                f.d = (int)u.x;
                 f.sp_off = u.y;
                 f.flags = u.z;
                 return f;
             };
-            auto attempt = [&](const Fast &p, int j) {
-                int d_addr = p.d_addr;
-                int nw = (int)(int8_t)(p.flags & 0xFFu);
-                int old = (int)(int8_t)((p.flags >> 8) & 0xFFu);
+            auto ld = [&](uint32_t addr) {
+                return *reinterpret_cast<const double *>(smem + addr);
+            };
+            Rec r0 = fetch(0), r1 = fetch(1);
+            // ln g at the next attempt's target, loaded before the current
+            // bin's ln g is written back (forwarded when the target is that bin)
+            double gnx = ld(baddr + (uint32_t)r0.d);
+            auto step = [&](int j) {
+                const Rec r2 = fetch(j + 2);
+                int d = r0.d;
+                int nw = (int)(int8_t)(r0.flags & 0xFFu);
+                int old = (int)(int8_t)((r0.flags >> 8) & 0xFFu);
+                double gn = pick(d == 0, gcur, gnx);
                 if (fmask & (kFirstLanes<G>::value << j)) {
                     // some group's attempt j is flagged: every group recomputes
                     // from its current spins, the flagged ones keep the result
-                    const int s = (int)stage[j].site;
+                    const int s = (int)(r0.sp_off - sp_base);
                     const Nbrs nb = neighbours(s, L, N, a.l_magic);
                     const int o2 = sp[s];
-                    const int n2 = new_state<MODEL>(o2, (p.flags >> 16) & 0x7Fu, q);
+                    const int n2 = new_state<MODEL>(o2, (r0.flags >> 16) & 0x7Fu, q);
                     const int d2 = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, o2, n2) *
                                    ADDR_PER_E;
-                    const bool f = (p.flags & 0x80000000u) != 0;
+                    const double g2 = ld(baddr + (uint32_t)d2);
+                    const bool f = (r0.flags & 0x80000000u) != 0;
                     old = f ? o2 : old;
                     nw = f ? n2 : nw;
-                    d_addr = f ? d2 : d_addr;
+                    d = f ? d2 : d;
+                    gn = pick(f, g2, gn);
                 }
                 // outside the window the target holds +inf: gcur - gn = -inf
                 // never exceeds ln u, so the move is rejected
-                const uint32_t naddr = baddr + (uint32_t)d_addr;
-                const double gn = *reinterpret_cast<const double *>(smem + naddr);
-                const bool accept = gcur - gn > p.thr;
-                smem[p.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
-                baddr = accept ? naddr : baddr;
-                gcur = accept ? gn : gcur;
-                gcur = gcur + p.lnf;
+                const bool accept = gcur - gn > r0.thr;
+                baddr = accept ? baddr + (uint32_t)d : baddr;
+                const double gsel = pick(accept, gn, gcur);
+                gnx = ld(baddr + (uint32_t)r1.d);
+                gcur = gsel + r0.lnf;
                 *reinterpret_cast<double *>(smem + baddr) = gcur;
+                smem[r0.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
                 // bin after attempt j and its acceptance, for lane j's H update
                 stage[j].site = baddr | (accept ? 1u : 0u);
+                r0 = r1;
+                r1 = r2;
             };
-            Fast f = fetch(0);
             if (n == G) {
 #pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    const Fast f1 = fetch(j + 1);
-                    attempt(f, j);
-                    f = f1;
-                }
+                for (int j = 0; j < G; ++j) step(j);
             } else {
-                for (int j = 0; j < n; ++j) {
-                    const Fast f1 = fetch(j + 1);
-                    attempt(f, j);
-                    f = f1;
-                }
+                for (int j = 0; j < n; ++j) step(j);
             }
         }
         // H of the block's attempts, one atomic per lane
