@@ -17,23 +17,30 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                     uint32_t k0, uint32_t k1)
+// rounds r0 .. r1-1 of Philox4x32-10 on (c, k); k is the key of round r0
+__device__ __forceinline__ void philox_rounds(U4 &c, uint32_t &k0, uint32_t &k1, int r0, int r1)
 {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
+    for (int r = r0; r < r1; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        c.y = (uint32_t)p1;
+        c.w = (uint32_t)p0;
+        c.x = n0;
+        c.z = n2;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+    U4 c{c0, c1, c2, c3};
+#pragma unroll
+    for (int r = 0; r < 10; ++r) philox_rounds(c, k0, k1, r, r + 1);
+    return c;
 }
 
 // uniform integer in [0, n) from one word
@@ -48,10 +55,15 @@ __device__ __forceinline__ uint32_t mulhi32(uint32_t word, uint32_t n)
 // s = (f-1)/(f+1) is summed as 2 (s + s z Q(z)), z = s^2,
 // Q(z) = 1/3 + z/5 + ... + z^10/23 (coefficients RN(1/(2i+1))).  ln 2 enters
 // split as LN2_HI (32 fractional bits, so e * LN2_HI is exact) + LN2_LO.
-__device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
+// Two halves, so that a caller can interleave them with other work:
+// ln_u_reduce gives s, z = s^2 and the exponent e, ln_u_sum the result.
+struct LnU {
+    double s, z;
+    int e;
+};
+
+__device__ __forceinline__ LnU ln_u_reduce(uint32_t hi, uint32_t lo)
 {
-    const double kLn2Hi = 0x1.62e42ffp-1;
-    const double kLn2Lo = -0x1.718432a1b0e26p-35;
     const double kSqrt2 = 0x1.6a09e667f3bcdp+0;
     const uint64_t n = ((((uint64_t)hi << 20) | (uint64_t)(lo >> 12)) << 1) | 1u;
     const int msb = 63 - __clzll((long long)n);
@@ -62,8 +74,19 @@ __device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
         f = f * 0.5;
         e = e + 1;
     }
-    const double s = (f - 1.0) / (f + 1.0);
-    const double z = s * s;
+    LnU r;
+    r.s = (f - 1.0) / (f + 1.0);
+    r.z = r.s * r.s;
+    r.e = e;
+    return r;
+}
+
+// second half: e ln 2 + 2 (s + s z Q(z))
+__device__ __forceinline__ double ln_u_sum(const LnU &a)
+{
+    const double kLn2Hi = 0x1.62e42ffp-1;
+    const double kLn2Lo = -0x1.718432a1b0e26p-35;
+    const double z = a.z, s = a.s;
     double Q = 1.0 / 23.0;
     Q = Q * z + 1.0 / 21.0;
     Q = Q * z + 1.0 / 19.0;
@@ -75,9 +98,14 @@ __device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
     Q = Q * z + 1.0 / 7.0;
     Q = Q * z + 1.0 / 5.0;
     Q = Q * z + 1.0 / 3.0;
-    const double ed = (double)e;
+    const double ed = (double)a.e;
     const double lnf = (s + s * (z * Q)) * 2.0;
     return ed * kLn2Hi + (ed * kLn2Lo + lnf);
+}
+
+__device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
+{
+    return ln_u_sum(ln_u_reduce(hi, lo));
 }
 
 // Neighbours of site i = r L + c on the L x L torus; the row is

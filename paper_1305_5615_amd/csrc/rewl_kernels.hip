@@ -317,19 +317,46 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         uint32_t r1;
         double thr;
     };
-    auto draw = [&](long long base) {
-        Draw d;
+    // a draw taken in 8 pieces (five of two Philox rounds each, then site and
+    // neighbours, then the two halves of ln u), so that the draws of the next
+    // block can be spread over the in-order pass of this one, where they fill
+    // the wait for each LDS round trip
+    struct DrawSt {
+        U4 c;
+        uint32_t k0, k1;
+        LnU lu;
+        Draw out;
+    };
+    auto draw_start = [&](long long base) {
+        DrawSt st;
         const unsigned long long c = t0 + (unsigned long long)base + gl;
-        const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u, a.key0, a.key1);
-        d.site = (int)mulhi32(r.x, (uint32_t)N);
-        d.r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(q - 1)) : 0u;
-        const Nbrs nb = neighbours(d.site, L, N, a.l_magic);
-        d.rt = nb.rt;
-        d.lf = nb.lf;
-        d.dn = nb.dn;
-        d.up = nb.up;
-        d.thr = ln_u(r.z, r.w);
-        return d;
+        st.c = U4{(uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 0u};
+        st.k0 = a.key0;
+        st.k1 = a.key1;
+        return st;
+    };
+    auto draw_piece = [&](DrawSt &st, int piece) {
+        if (piece < 5) {
+            philox_rounds(st.c, st.k0, st.k1, 2 * piece, 2 * piece + 2);
+        } else if (piece == 5) {
+            st.out.site = (int)mulhi32(st.c.x, (uint32_t)N);
+            st.out.r1 = (MODEL == kPotts) ? 1u + mulhi32(st.c.y, (uint32_t)(q - 1)) : 0u;
+            const Nbrs nb = neighbours(st.out.site, L, N, a.l_magic);
+            st.out.rt = nb.rt;
+            st.out.lf = nb.lf;
+            st.out.dn = nb.dn;
+            st.out.up = nb.up;
+        } else if (piece == 6) {
+            st.lu = ln_u_reduce(st.c.z, st.c.w);
+        } else {
+            st.out.thr = ln_u_sum(st.lu);
+        }
+    };
+    auto draw = [&](long long base) {
+        DrawSt st = draw_start(base);
+#pragma unroll
+        for (int piece = 0; piece < 8; ++piece) draw_piece(st, piece);
+        return st.out;
     };
     Draw cur = draw(0);
 
@@ -359,8 +386,16 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         }
         __syncthreads();
         if (active) tag[cur.site] = (TagT)0;
-        // draws of the next block do not depend on the walk and overlap with it
-        const Draw nxt_draw = draw(base + G);
+        // draws of the next block: with several walkers per wave, spread over
+        // the in-order pass below; with one, whole here (the compiler then
+        // interleaves them with the 64-attempt pass by itself, which measured
+        // faster than the spread)
+        constexpr bool kSpread = G < 64;
+        DrawSt nxt = draw_start(base + G);
+        if (!kSpread) {
+#pragma unroll
+            for (int piece = 0; piece < 8; ++piece) draw_piece(nxt, piece);
+        }
         // flagged attempts of the block, one bit per lane (wave-uniform)
         const uint64_t fmask = __builtin_amdgcn_ballot_w64(active && (stage[gl].flags >> 31));
         if (live) {
@@ -433,7 +468,16 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             };
             if (n == G) {
 #pragma unroll
-                for (int j = 0; j < G; ++j) step(j);
+                for (int j = 0; j < G; ++j) {
+                    step(j);
+                    // pieces ceil(8j/G) .. ceil(8(j+1)/G)-1 of the next draws
+                    if (kSpread) {
+#pragma unroll
+                        for (int piece = (8 * j + G - 1) / G; piece < (8 * (j + 1) + G - 1) / G;
+                             ++piece)
+                            draw_piece(nxt, piece);
+                    }
+                }
             } else {
                 for (int j = 0; j < n; ++j) step(j);
             }
@@ -444,7 +488,8 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             atomicAdd(&H_s[((v & ~7u) - lng_base) >> 3], 1u);
             acc += v & 1u;
         }
-        cur = nxt_draw;
+        // (a block shorter than G is the last one: its next draws are unused)
+        cur = nxt.out;
         __syncthreads();
     }
 
