@@ -106,7 +106,8 @@ def percentile(xs, q):
 
 def run_kwargs(p):
     keys = ("model", "L", "q", "couplings", "e_min", "e_max", "n_windows", "overlap",
-            "walkers_per_window", "flatness", "lnf_init", "lnf_final", "S", "seed")
+            "walkers_per_window", "flatness", "lnf_init", "lnf_final", "S", "seed", "schedule",
+            "windows")
     return {k: p[k] for k in keys if k in p}
 
 
@@ -382,6 +383,84 @@ def served(rewl, args):
     print(json.dumps(out), flush=True)
 
 
+def balanced(rewl, args):
+    """Time-to-DOS with run-time balanced windows (a pre-run on the equal
+    partition to every window's first merge, then the run on the derived
+    windows) against the plain run on the equal partition, same seeds."""
+    import torch
+
+    from workloads import run_params
+
+    out = {"metric": "time-to-converged ln g, run-time balanced vs equal windows",
+           "workload": WORKLOAD_TEXT[args.workload], "unit": "s", "runs": []}
+    for i in range(args.steps):
+        p = run_params(args.workload, seed=1 + i)
+        eq = gpu_full_run(rewl, p, args.max_rounds)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lo, hi, pre_rounds = rewl.balanced_windows(chunk=16, **run_kwargs(p))
+        torch.cuda.synchronize()
+        t_pre = time.perf_counter() - t0
+        bal = gpu_full_run(rewl, dict(p, windows=(lo, hi)), args.max_rounds)
+        rec = {"seed": p["seed"],
+               "equal": {"seconds": eq["seconds"], "rounds": eq["rounds"],
+                         "finish_rounds": eq["finish"],
+                         "max_abs_dlng_vs_exact": exact_error(p, eq["lng"])},
+               "balanced": {"pre_run_seconds": t_pre, "pre_run_rounds": pre_rounds,
+                            "run_seconds": bal["seconds"], "seconds": t_pre + bal["seconds"],
+                            "rounds": bal["rounds"], "finish_rounds": bal["finish"],
+                            "windows": [[int(a), int(b)] for a, b in zip(lo, hi)],
+                            "max_abs_dlng_vs_exact": exact_error(p, bal["lng"])}}
+        out["runs"].append(rec)
+        log(f"seed {p['seed']}: equal {eq['seconds']:.1f} s ({eq['rounds']} rounds), balanced "
+            f"{t_pre:.1f} + {bal['seconds']:.1f} s ({bal['rounds']} rounds)")
+    print(json.dumps(out), flush=True)
+
+
+def errors(rewl, args):
+    """Independent-run error bars and their dependence on the walkers per
+    window m (and a weaker flatness with larger m): for each setting, R seeds
+    of the workload in one batch to convergence, the jackknife mean and error
+    of ln g per bin, compared with the exact DOS where one is stored."""
+    import numpy as np
+    import torch
+
+    from workloads import run_params
+
+    R = args.errors
+    settings = [(1, 0.8), (2, 0.8), (4, 0.8), (8, 0.8), (8, 0.6)]
+    out = {"metric": "jackknife error of ln g over independent runs vs walkers per window",
+           "workload": WORKLOAD_TEXT[args.workload], "runs_per_setting": R, "settings": []}
+    for m, flat in settings:
+        params = [dict(run_params(args.workload, seed=101 + i), walkers_per_window=m,
+                       flatness=flat) for i in range(R)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=1, graph_rounds=16)
+        issued = 0
+        while not b.done().all() and issued < args.max_rounds:
+            b.step(256)
+            issued += 256
+        lngs = np.array([b[i].lng() for i in range(R)])
+        rounds = [max(w["finish_round"] for w in b[i].windows()) + 1 for i in range(R)]
+        wall = time.perf_counter() - t0
+        b.close()
+        mean, err = rewl.jackknife(lngs)
+        fin = np.isfinite(mean)
+        rec = {"walkers_per_window": m, "flatness": flat, "wall_s": wall,
+               "rounds_mean": float(np.mean(rounds)),
+               "jackknife_err_mean": float(np.nanmean(err[fin])),
+               "jackknife_err_max": float(np.nanmax(err[fin]))}
+        exact = [exact_error(params[0], lg) for lg in lngs]
+        if exact[0] is not None:
+            rec["max_abs_dlng_vs_exact_per_run_mean"] = float(np.mean(exact))
+            rec["max_abs_dlng_vs_exact_of_mean"] = exact_error(params[0], mean)
+        out["settings"].append(rec)
+        log(f"m={m} p={flat}: {wall:.1f} s, rounds {np.mean(rounds):.0f}, "
+            f"jackknife err mean {rec['jackknife_err_mean']:.4f}")
+    print(json.dumps(out), flush=True)
+
+
 def calibrate_copy(mb):
     """One device-to-device copy of `mb` MiB (read mb, write mb) for scaling
     the FETCH_SIZE / WRITE_SIZE counters."""
@@ -422,6 +501,12 @@ def main():
     ap.add_argument("--served-sizes", default="small", choices=("small", "full"),
                     help="served mode: lattice sizes of the request mix")
     ap.add_argument("--budget-mb", type=int, default=4096, help="served mode: device budget")
+    ap.add_argument("--balanced", action="store_true",
+                    help="time-to-DOS with run-time balanced windows vs equal windows "
+                         "(--steps seeds)")
+    ap.add_argument("--errors", type=int, default=0,
+                    help="error-bar mode: this many independent runs per walkers-per-window "
+                         "setting")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="counter calibration: one device copy of this many MiB")
     args = ap.parse_args()
@@ -445,6 +530,12 @@ def main():
         return
     if args.copy_mb > 0:
         calibrate_copy(args.copy_mb)
+        return
+    if args.balanced:
+        balanced(rewl, args)
+        return
+    if args.errors > 1:
+        errors(rewl, args)
         return
 
     base = dict(run_params(args.workload, seed=1))

@@ -90,6 +90,13 @@ typedef struct rewl_params {
     int64_t attempts_per_round;
     uint64_t seed;
     int schedule;  /* REWL_HALVING or REWL_ONE_OVER_T */
+    /* Explicit windows (both or neither; NULL: the equal partition): n_windows
+     * first and last bins each, bin b = (E - e_min) / step after the range is
+     * aligned; they must start at bin 0, end at the last bin, have increasing
+     * starts and ends, >= 2 bins each and >= 2 bins shared by neighbours.
+     * Copied by the calls that take a rewl_params. */
+    const int64_t *window_lo;
+    const int64_t *window_hi;
 } rewl_params;
 
 typedef struct rewl_ctx rewl_ctx; /* opaque, owned by the library */
@@ -163,6 +170,42 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
  * rewl_get_timing synchronises the stream and returns the summed elapsed time
  * of those launches (milliseconds) and their number since the last
  * rewl_set_timing.  Costs two event records per round; off by default. */
+/* Round in which each window first merged (halved ln f), -1 where it has not
+ * yet: out[k] for k < min(cap, n_windows).  With a run on the equal partition
+ * stepped until every entry is >= 0, these are the first-iteration times that
+ * rewl_partition_balanced takes (as first + 1 rounds). */
+int rewl_get_first_merge(rewl_ctx *h, int64_t *out, int cap);
+
+/* Run-time balanced windows (the paper's Fig. 1b and its scaling discussion:
+ * windows chosen so that all of them complete the first WL iteration after
+ * the same number of sweeps, estimated from a pre-run on the equal
+ * partition).  Host-only; all arrays are caller-owned host memory.
+ *   n_bins, n_windows, overlap: the new partition (n_windows >= 1, 0 < o < 1);
+ *   pre_lo/pre_hi (pre_windows entries): the pre-run's windows, a valid
+ *   partition of the same bins; first_rounds: rounds each pre-run window took
+ *   for its first iteration (>= 1).
+ * Each bin gets the first-iteration time density t(b) = mean of
+ * first_rounds[k] / (pre_hi[k] - pre_lo[k] + 1) over the pre-run windows that
+ * contain it; bins are points on the axis F(0) = 0,
+ * F(b+1) = F(b) + (t(b) + t(b+1)) / 2, and the result is the equal partition
+ * of that axis: x_k = k (1-o) w, w = F(last) / (1 + (n_windows-1)(1-o)), lo_k =
+ * last bin with F <= x_k, hi_k = first bin with F >= x_k + w (the last bin for
+ * k = n_windows - 1).  A uniform density gives the equal partition exactly.
+ * Returns REWL_EINVAL for bad arguments or when the result is not a valid
+ * partition (windows narrower than 2 bins or overlapping by fewer). */
+int rewl_partition_balanced(int64_t n_bins, int n_windows, double overlap, int pre_windows,
+                            const int64_t *pre_lo, const int64_t *pre_hi,
+                            const int64_t *first_rounds, int64_t *lo, int64_t *hi);
+
+/* Jackknife (leave-one-out) mean and error of ln g per bin over independent
+ * runs, the paper's resampling estimate of statistical errors.  Host-only.
+ * lng: runs x n_bins doubles, row r = run r's stitched, normalised ln g
+ * (caller-owned); mean, err: n_bins each (caller-owned).  For bin b with
+ * values x_r: mean = sum_r x_r / R; theta_i = (sum_r x_r - x_i) / (R-1);
+ * err = sqrt((R-1)/R * sum_i (theta_i - mean_i theta_i)^2).  A bin that any
+ * run left unvisited (-inf) gets mean -inf and err NaN.  runs >= 2. */
+int rewl_jackknife(const double *lng, int runs, int64_t n_bins, double *mean, double *err);
+
 int rewl_set_timing(rewl_ctx *h, int on);
 int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches);
 

@@ -42,7 +42,9 @@ def lib():
         i64, u64, i32, u32, dbl = C.c_int64, C.c_uint64, C.c_int, C.c_uint32, C.c_double
         P = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(P), i32, i32, i32, P, i64, i64, i32, dbl, i32,
-                                 dbl, dbl, dbl, i64, u64, i32, i32]
+                                 dbl, dbl, dbl, i64, u64, i32, i32, P, P]
+        L.orc_first_merge.argtypes = [P, P]
+        L.orc_partition_balanced.argtypes = [i64, i32, dbl, i32, P, P, P, P, P]
         L.orc_destroy.argtypes = [P]
         L.orc_step.argtypes = [P, i64]
         L.orc_run_to.argtypes = [P, i64]
@@ -100,6 +102,21 @@ def partition(n_bins, n_windows, overlap):
     return lo, hi
 
 
+def partition_balanced(n_bins, n_windows, overlap, pre_lo, pre_hi, first_rounds):
+    """Run-time balanced windows from a pre-run's windows and first-iteration
+    rounds (T_k = rounds until window k's first merge)."""
+    pl = np.ascontiguousarray(pre_lo, dtype=np.int64)
+    ph = np.ascontiguousarray(pre_hi, dtype=np.int64)
+    T = np.ascontiguousarray(first_rounds, dtype=np.int64)
+    lo = np.zeros(n_windows, dtype=np.int64)
+    hi = np.zeros(n_windows, dtype=np.int64)
+    rc = lib().orc_partition_balanced(n_bins, n_windows, overlap, len(pl), _p(pl), _p(ph), _p(T),
+                                      _p(lo), _p(hi))
+    if rc:
+        raise ValueError("invalid balanced partition")
+    return lo, hi
+
+
 def stitch(lo, hi, pieces, visited, n_bins):
     lo = np.ascontiguousarray(lo, dtype=np.int64)
     hi = np.ascontiguousarray(hi, dtype=np.int64)
@@ -125,17 +142,24 @@ class Run:
 
     def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                  overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                 lnf_final=1e-6, S=10_000, seed=1, n_threads=1, schedule="halving"):
+                 lnf_final=1e-6, S=10_000, seed=1, n_threads=1, schedule="halving",
+                 windows=None):
         N = L * L
         if e_min is None:
             e_min = -2 * N
         if e_max is None:
             e_max = 0 if model == "potts" else 2 * N
         J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
+        wl = wh = None
+        if windows is not None:
+            wl = np.ascontiguousarray(windows[0], dtype=np.int64)
+            wh = np.ascontiguousarray(windows[1], dtype=np.int64)
+            if len(wl) != n_windows or len(wh) != n_windows:
+                raise OracleError(-1, "orc_create")
         h = C.c_void_p()
         rc = lib().orc_create(C.byref(h), MODELS[model], L, q, _p(J), e_min, e_max, n_windows,
                               overlap, walkers_per_window, flatness, lnf_init, lnf_final, S,
-                              seed, n_threads, SCHEDULES[schedule])
+                              seed, n_threads, SCHEDULES[schedule], _p(wl), _p(wh))
         if rc:
             raise OracleError(rc, "orc_create")
         self._h = h
@@ -201,6 +225,11 @@ class Run:
 
     def energies(self):
         return self.e_min + self.e_step * np.arange(self.n_bins)
+
+    def first_merge(self):
+        out = np.zeros(self.h, dtype=np.int64)
+        lib().orc_first_merge(self._h, _p(out))
+        return out
 
     def stats(self):
         v = [C.c_uint64() for _ in range(4)]

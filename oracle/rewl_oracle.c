@@ -200,6 +200,70 @@ int orc_partition(int64_t B, int h, double o, int64_t *lo, int64_t *hi)
     return 0;
 }
 
+/* Check a partition: h windows of >= 2 bins from bin 0 to bin B-1, starts and
+ * ends increasing, adjacent windows sharing >= 2 bins. */
+static int partition_ok(int64_t B, int h, const int64_t *lo, const int64_t *hi)
+{
+    if (h < 1 || lo[0] != 0 || hi[h - 1] != B - 1) return 0;
+    for (int k = 0; k < h; ++k) {
+        if (lo[k] < 0 || hi[k] > B - 1 || hi[k] - lo[k] + 1 < 2) return 0;
+        if (k + 1 < h) {
+            if (lo[k + 1] <= lo[k] || hi[k + 1] <= hi[k]) return 0;
+            if (hi[k] - lo[k + 1] + 1 < 2) return 0;
+        }
+    }
+    return 1;
+}
+
+/* Run-time balanced partition (the paper's Fig. 1b and its scaling
+ * discussion: windows chosen so that all finish the first WL iteration after
+ * the same number of sweeps, estimated from a pre-run on the equal
+ * partition).  The pre-run's window k (bins pre_lo[k]..pre_hi[k]) needed T_k
+ * rounds for its first iteration; a bin's first-iteration time density t(b)
+ * is the mean of T_k / W_k over the pre-run windows that contain it.  Bins are
+ * points on a time axis F with F(0) = 0 and F(b+1) = F(b) + (t(b) + t(b+1))/2,
+ * and the new windows are the equal partition of that axis: window k covers
+ * F in [x_k, x_k + w], x_k = k (1-o) w, w = F(B-1) / (1 + (h-1)(1-o)); lo_k is
+ * the last bin with F <= x_k, hi_k the first bin with F >= x_k + w (B-1 for
+ * the last window).  With t = 1 everywhere this is orc_partition exactly. */
+int orc_partition_balanced(int64_t B, int h, double o, int pre_h, const int64_t *pre_lo,
+                           const int64_t *pre_hi, const int64_t *T, int64_t *lo, int64_t *hi)
+{
+    if (B < 2 || h < 1 || pre_h < 1 || !(o > 0.0 && o < 1.0)) return -1;
+    if (!partition_ok(B, pre_h, pre_lo, pre_hi)) return -1;
+    for (int k = 0; k < pre_h; ++k) if (T[k] < 1) return -1;
+    double *t = malloc((size_t)B * sizeof(double));
+    double *F = malloc((size_t)B * sizeof(double));
+    if (!t || !F) { free(t); free(F); return -2; }
+    for (int64_t b = 0; b < B; ++b) {
+        double sum = 0.0;
+        int n = 0;
+        for (int k = 0; k < pre_h; ++k) {
+            if (b < pre_lo[k] || b > pre_hi[k]) continue;
+            sum = sum + (double)T[k] / (double)(pre_hi[k] - pre_lo[k] + 1);
+            n += 1;
+        }
+        t[b] = sum / (double)n;
+    }
+    F[0] = 0.0;
+    for (int64_t b = 0; b + 1 < B; ++b) F[b + 1] = F[b] + (t[b] + t[b + 1]) * 0.5;
+    double w = F[B - 1] / (1.0 + (double)(h - 1) * (1.0 - o));
+    for (int k = 0; k < h; ++k) {
+        double x = ((double)k * (1.0 - o)) * w;
+        double y = x + w;
+        int64_t a = 0;
+        while (a + 1 < B && F[a + 1] <= x) ++a;
+        int64_t e = 0;
+        while (e < B - 1 && F[e] < y) ++e;
+        lo[k] = a;
+        hi[k] = e;
+    }
+    hi[h - 1] = B - 1;
+    free(t);
+    free(F);
+    return partition_ok(B, h, lo, hi) ? 0 : -1;
+}
+
 /* ------------------------------------------------------------------- run --- */
 struct orc_run {
     int model, L, q, N, h, m, nw, n_threads;
@@ -215,6 +279,7 @@ struct orc_run {
     int *done;          /* h */
     int *phase;         /* h: 1 once the window runs the 1/t rule */
     int64_t *finish;    /* h: round in which the window finished, -1 before */
+    int64_t *first;     /* h: round of the window's first merge, -1 before */
     int8_t *spins;      /* nw * N */
     int64_t *E;         /* nw */
     uint64_t *t;        /* nw */
@@ -240,7 +305,7 @@ void orc_destroy(orc_run *run)
 {
     if (!run) return;
     free(run->J); free(run->lo); free(run->hi); free(run->lnf); free(run->done); free(run->phase);
-    free(run->finish); free(run->spins); free(run->E); free(run->t); free(run->flat);
+    free(run->finish); free(run->first); free(run->spins); free(run->E); free(run->t); free(run->flat);
     free(run->lng); free(run->H); free(run->vis); free(run->n_acc);
     free(run);
 }
@@ -299,7 +364,7 @@ static int init_walker(orc_run *run, int w)
 int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
                int64_t e_min, int64_t e_max, int h, double o, int m, double p,
                double lnf_init, double lnf_final, int64_t S, uint64_t seed, int n_threads,
-               int schedule)
+               int schedule, const int64_t *win_lo, const int64_t *win_hi)
 {
     *out = NULL;
     if (model < 0 || model > 2 || L < 3 || L > 256 || h < 1 || m < 1 || S < 1) return -1;
@@ -341,7 +406,13 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->lnf_final = lnf_final; run->seed = seed; run->schedule = schedule;
     run->lo = calloc(h, sizeof(int64_t)); run->hi = calloc(h, sizeof(int64_t));
     if (!run->lo || !run->hi) { orc_destroy(run); return -2; }
-    if (orc_partition(run->B, h, o, run->lo, run->hi)) { orc_destroy(run); return -1; }
+    if (win_lo && win_hi) {
+        for (int k = 0; k < h; ++k) { run->lo[k] = win_lo[k]; run->hi[k] = win_hi[k]; }
+        if (!partition_ok(run->B, h, run->lo, run->hi)) { orc_destroy(run); return -1; }
+    } else if (orc_partition(run->B, h, o, run->lo, run->hi)) {
+        orc_destroy(run);
+        return -1;
+    }
     run->Wmax = 0;
     for (int k = 0; k < h; ++k) if (wsize(run, k) > run->Wmax) run->Wmax = wsize(run, k);
     size_t nw = (size_t)run->nw;
@@ -349,19 +420,21 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->lnf = calloc(h, sizeof(double)); run->done = calloc(h, sizeof(int));
     run->phase = calloc(h, sizeof(int));
     run->finish = calloc(h, sizeof(int64_t));
+    run->first = calloc(h, sizeof(int64_t));
     run->spins = calloc(nw * N, 1); run->E = calloc(nw, sizeof(int64_t));
     run->t = calloc(nw, sizeof(uint64_t)); run->flat = calloc(nw, sizeof(int));
     run->lng = calloc(nw * run->Wmax, sizeof(double));
     run->H = calloc(nw * run->Wmax, sizeof(uint32_t));
     run->vis = calloc(nw * run->Wmax, 1);
     run->n_acc = calloc(nw, sizeof(uint64_t));
-    if (!run->J || !run->lnf || !run->done || !run->phase || !run->finish || !run->spins || !run->E ||
+    if (!run->J || !run->lnf || !run->done || !run->phase || !run->finish || !run->first ||
+        !run->spins || !run->E ||
         !run->t || !run->flat || !run->lng || !run->H || !run->vis || !run->n_acc) {
         orc_destroy(run);
         return -2;
     }
     if (model == ORC_EA) memcpy(run->J, couplings, 2 * (size_t)N);
-    for (int k = 0; k < h; ++k) { run->lnf[k] = lnf_init; run->finish[k] = -1; }
+    for (int k = 0; k < h; ++k) { run->lnf[k] = lnf_init; run->finish[k] = -1; run->first[k] = -1; }
     for (int w = 0; w < run->nw; ++w) {
         int rc = init_walker(run, w);
         if (rc) { orc_destroy(run); return rc; }
@@ -455,6 +528,7 @@ static void merge_window(orc_run *run, int k, int64_t round)
         }
     }
     for (int s = 0; s < m; ++s) run->flat[k * m + s] = 0;
+    if (run->first[k] < 0) run->first[k] = round;
     double Wt = (double)W / (double)run->t[k * m]; /* the window's walkers share t */
     if (run->phase[k]) {
         run->lnf[k] = Wt;
@@ -618,6 +692,11 @@ int orc_set_lng(orc_run *run, int w, const double *lng)
         run->vis[(size_t)w * run->Wmax + b] = lng[b] > 0.0;
     }
     return 0;
+}
+
+void orc_first_merge(const orc_run *run, int64_t *out)
+{
+    for (int k = 0; k < run->h; ++k) out[k] = run->first[k];
 }
 
 void orc_stats(const orc_run *run, uint64_t *attempts, uint64_t *accepts, uint64_t *ex_prop,

@@ -29,11 +29,15 @@ typedef struct orc_run orc_run;
  * energy class of the couplings.  lnf_init is the first ln f; S the number of
  * attempts per walker per round; n_threads the OpenMP threads used by the
  * sweep (0 = runtime default); schedule 0 halves ln f at every merge, 1 halves
- * it until it would drop below W/t and then follows W/t (the 1/t rule). */
+ * it until it would drop below W/t and then follows W/t (the 1/t rule).
+ * win_lo/win_hi (both or neither): explicit windows in bins, replacing the
+ * equal partition; they must run from bin 0 to the last bin with increasing
+ * starts and ends, >= 2 bins each and >= 2 shared by neighbours. */
 int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
                int64_t e_min, int64_t e_max, int n_windows, double overlap,
                int walkers_per_window, double flatness, double lnf_init,
-               double lnf_final, int64_t S, uint64_t seed, int n_threads, int schedule);
+               double lnf_final, int64_t S, uint64_t seed, int n_threads, int schedule,
+               const int64_t *win_lo, const int64_t *win_hi);
 void orc_destroy(orc_run *run);
 
 /* Advance exactly `rounds` rounds (rounds of a finished run change nothing). */
@@ -56,6 +60,8 @@ int orc_walker(const orc_run *run, int w, int8_t *spins, int64_t *E, uint64_t *t
 int orc_set_lng(orc_run *run, int w, const double *lng);
 /* Stitched, normalised ln g over all bins; unvisited bins = -inf. */
 int orc_get_lng(orc_run *run, double *out, int64_t cap);
+/* Round of each window's first merge (-1 where none happened yet). */
+void orc_first_merge(const orc_run *run, int64_t *out);
 /* Counters: accepted sweep moves, exchange proposals and acceptances. */
 void orc_stats(const orc_run *run, uint64_t *attempts, uint64_t *accepts,
                uint64_t *ex_prop, uint64_t *ex_acc);
@@ -66,6 +72,10 @@ double orc_ln_u(double u);
 double orc_uniform(uint32_t hi, uint32_t lo);
 int64_t orc_energy(int model, int L, int q, const int8_t *spins, const int8_t *couplings);
 int orc_partition(int64_t n_bins, int n_windows, double overlap, int64_t *lo, int64_t *hi);
+/* Run-time balanced partition from a pre-run's windows and first-iteration
+ * rounds T (see rewl_oracle.c). */
+int orc_partition_balanced(int64_t B, int h, double o, int pre_h, const int64_t *pre_lo,
+                           const int64_t *pre_hi, const int64_t *T, int64_t *lo, int64_t *hi);
 int orc_stitch(int n_windows, const int64_t *lo, const int64_t *hi, const double *pieces,
                int64_t stride, const uint8_t *visited, int64_t n_bins, double *out,
                int64_t *joins);

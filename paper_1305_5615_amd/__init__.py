@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("walkers_per_window", C.c_int), ("flatness", C.c_double),
                 ("lnf_init", C.c_double), ("lnf_final", C.c_double),
                 ("attempts_per_round", C.c_int64), ("seed", C.c_uint64),
-                ("schedule", C.c_int)]
+                ("schedule", C.c_int), ("window_lo", C.c_void_p), ("window_hi", C.c_void_p)]
 
 SCHEDULES = {"halving": 0, "1/t": 1}
 
@@ -66,6 +66,9 @@ def lib():
         L.rewl_destroy.argtypes = [P]
         L.rewl_destroy.restype = None
         L.rewl_set_timing.argtypes = [P, i32]
+        L.rewl_get_first_merge.argtypes = [P, P, i32]
+        L.rewl_jackknife.argtypes = [P, i32, i64, P, P]
+        L.rewl_partition_balanced.argtypes = [i64, i32, dbl, i32, P, P, P, P, P]
         L.rewl_get_timing.argtypes = [P, C.POINTER(dbl), C.POINTER(i64)]
         L.rewl_batch_create.argtypes = [C.POINTER(P), P, i32, i32, P]
         L.rewl_batch_get_run.argtypes = [P, i32, C.POINTER(P)]
@@ -105,17 +108,80 @@ def _p(a):
 
 def make_params(model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                 overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                lnf_final=1e-6, S=10_000, seed=1, schedule="halving"):
+                lnf_final=1e-6, S=10_000, seed=1, schedule="halving", windows=None):
+    """rewl_params for the arguments, and the arrays it points to (keep them
+    alive until the library has copied them).  windows: (lo, hi) bin arrays of
+    an explicit partition, or None for the equal partition."""
     N = L * L
     if e_min is None:
         e_min = -2 * N
     if e_max is None:
         e_max = 0 if model == "potts" else 2 * N
     J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
+    wl = wh = None
+    if windows is not None:
+        wl = np.ascontiguousarray(windows[0], dtype=np.int64)
+        wh = np.ascontiguousarray(windows[1], dtype=np.int64)
+        if len(wl) != n_windows or len(wh) != n_windows:
+            raise RewlError(-1, "make_params", "windows must have n_windows entries")
     p = Params(MODELS[model], L, q, None if J is None else J.ctypes.data, int(e_min),
                int(e_max), n_windows, overlap, walkers_per_window, flatness, lnf_init,
-               lnf_final, int(S), int(seed), SCHEDULES[schedule])
-    return p, J
+               lnf_final, int(S), int(seed), SCHEDULES[schedule],
+               None if wl is None else wl.ctypes.data, None if wh is None else wh.ctypes.data)
+    return p, (J, wl, wh)
+
+
+def partition_balanced(n_bins, n_windows, overlap, pre_lo, pre_hi, first_rounds):
+    """Run-time balanced windows (rewl_partition_balanced) from a pre-run's
+    windows and first-iteration rounds."""
+    pl = np.ascontiguousarray(pre_lo, dtype=np.int64)
+    ph = np.ascontiguousarray(pre_hi, dtype=np.int64)
+    T = np.ascontiguousarray(first_rounds, dtype=np.int64)
+    lo = np.zeros(n_windows, dtype=np.int64)
+    hi = np.zeros(n_windows, dtype=np.int64)
+    _check(lib().rewl_partition_balanced(int(n_bins), n_windows, float(overlap), len(pl), _p(pl),
+                                         _p(ph), _p(T), _p(lo), _p(hi)),
+           "rewl_partition_balanced")
+    return lo, hi
+
+
+def jackknife(lng_runs):
+    """Jackknife mean and error of ln g per bin over independent runs
+    (rewl_jackknife); lng_runs: runs x bins."""
+    x = np.ascontiguousarray(lng_runs, dtype=np.float64)
+    mean = np.empty(x.shape[1])
+    err = np.empty(x.shape[1])
+    _check(lib().rewl_jackknife(_p(x), x.shape[0], x.shape[1], _p(mean), _p(err)),
+           "rewl_jackknife")
+    return mean, err
+
+
+def balanced_windows(chunk=16, max_rounds=1_000_000, **kw):
+    """Run-time balanced windows for the run described by kw: a pre-run on the
+    equal partition (same parameters and seed) is stepped `chunk` rounds at a
+    time until every window has merged once; each window's first iteration
+    took first_merge + 1 rounds, which rewl_partition_balanced turns into the
+    new windows.  Returns (lo, hi, pre-run rounds stepped)."""
+    kw = {k: v for k, v in kw.items() if k != "windows"}
+    pre = Run(**kw)
+    try:
+        issued = 0
+        while True:
+            f = pre.first_merge()
+            if (f >= 0).all():
+                break
+            if issued >= max_rounds:
+                raise RewlError(1, "balanced_windows", "pre-run did not finish its first iteration")
+            pre.step(chunk)
+            issued += chunk
+        wins = pre.windows()
+        lo_pre = np.array([w["lo"] for w in wins], dtype=np.int64)
+        hi_pre = np.array([w["hi"] for w in wins], dtype=np.int64)
+        lo, hi = partition_balanced(pre.n_bins, pre.h, kw.get("overlap", 0.75), lo_pre, hi_pre,
+                                    f + 1)
+    finally:
+        pre.close()
+    return lo, hi, issued
 
 
 def footprint(**kw):
@@ -157,6 +223,12 @@ class RunView:
         return {"lo": lo.value, "hi": hi.value, "lnf": lnf.value, "done": bool(done.value),
                 "finish_round": fin.value}
 
+    def first_merge(self):
+        """Round of each window's first merge (-1 where none yet)."""
+        out = np.zeros(self.h, dtype=np.int64)
+        _check(lib().rewl_get_first_merge(self._h, _p(out), self.h), "rewl_get_first_merge")
+        return out
+
     def windows(self):
         return [self.window(k) for k in range(self.h)]
 
@@ -191,13 +263,15 @@ class Run(RunView):
 
     def __init__(self, model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows=4,
                  overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
-                 lnf_final=1e-6, S=10_000, seed=1, schedule="halving", stream=None):
+                 lnf_final=1e-6, S=10_000, seed=1, schedule="halving", windows=None,
+                 stream=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
-        p, J = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
-                           walkers_per_window, flatness, lnf_init, lnf_final, S, seed, schedule)
+        p, keep = make_params(model, L, q, couplings, e_min, e_max, n_windows, overlap,
+                              walkers_per_window, flatness, lnf_init, lnf_final, S, seed,
+                              schedule, windows)
         dev, lds = C.c_size_t(), C.c_size_t()
         _check(lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)), "rewl_footprint")
         self._buf = torch.empty(dev.value, dtype=torch.uint8, device="cuda")

@@ -75,6 +75,25 @@ int make_windows(int64_t B, int h, double o, std::vector<int64_t> &lo, std::vect
     return REWL_OK;
 }
 
+// An explicit partition: n windows from bin 0 to bin B-1, starts and ends
+// increasing, >= 2 bins each, >= 2 bins shared by neighbours.
+int check_windows(int64_t B, int n, const std::vector<int64_t> &lo, const std::vector<int64_t> &hi)
+{
+    if (n < 1 || lo[0] != 0 || hi[n - 1] != B - 1)
+        return fail(REWL_EINVAL, "windows must run from the first to the last bin");
+    for (int k = 0; k < n; ++k) {
+        if (lo[k] < 0 || hi[k] > B - 1 || hi[k] - lo[k] + 1 < 2)
+            return fail(REWL_EINVAL, "a window is narrower than 2 bins");
+        if (k + 1 < n) {
+            if (lo[k + 1] <= lo[k] || hi[k + 1] <= hi[k])
+                return fail(REWL_EINVAL, "windows are not increasing");
+            if (hi[k] - lo[k + 1] + 1 < 2)
+                return fail(REWL_EINVAL, "adjacent windows overlap by fewer than 2 bins");
+        }
+    }
+    return REWL_OK;
+}
+
 int validate(const rewl_params *p, Geometry &g)
 {
     if (!p) return fail(REWL_EINVAL, "params is NULL");
@@ -123,7 +142,16 @@ int validate(const rewl_params *p, Geometry &g)
     g.e_min = e_min;
     g.e_max = e_max;
     g.B = (e_max - e_min) / st + 1;
-    int rc = make_windows(g.B, p->n_windows, p->overlap, g.lo, g.hi);
+    int rc;
+    if (p->window_lo || p->window_hi) {
+        if (!p->window_lo || !p->window_hi)
+            return fail(REWL_EINVAL, "window_lo and window_hi go together");
+        g.lo.assign(p->window_lo, p->window_lo + p->n_windows);
+        g.hi.assign(p->window_hi, p->window_hi + p->n_windows);
+        rc = check_windows(g.B, p->n_windows, g.lo, g.hi);
+    } else {
+        rc = make_windows(g.B, p->n_windows, p->overlap, g.lo, g.hi);
+    }
     if (rc) return rc;
     g.Wmax = 0;
     for (int k = 0; k < p->n_windows; ++k)
@@ -137,8 +165,8 @@ int validate(const rewl_params *p, Geometry &g)
 
 // Byte offsets of the arrays inside the device allocation.
 struct Layout {
-    size_t spins, E, t, flat, lng, H, n_acc, lnf, done, phase, finish, lo, hi, ex_prop, ex_acc,
-        J4, round, status, total;
+    size_t spins, E, t, flat, lng, H, n_acc, lnf, done, phase, finish, first, lo, hi, ex_prop,
+        ex_acc, J4, round, status, total;
 };
 
 Layout layout(const rewl_params *p, const Geometry &g)
@@ -162,6 +190,7 @@ Layout layout(const rewl_params *p, const Geometry &g)
     l.done = take(h * 4);
     l.phase = take(h * 4);
     l.finish = take(h * 8);
+    l.first = take(h * 8);
     l.lo = take(h * 4);
     l.hi = take(h * 4);
     l.ex_prop = take(h * 8);
@@ -481,6 +510,9 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     h->p = *p;
     h->g = g;
     h->l = layout(p, g);
+    // the windows live in the geometry from here on
+    h->p.window_lo = h->g.lo.data();
+    h->p.window_hi = h->g.hi.data();
     if (p->model == REWL_EA) {
         h->couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
         h->p.couplings = h->couplings.data();
@@ -531,6 +563,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     d.done = (int *)(b + h->l.done);
     d.phase = (int *)(b + h->l.phase);
     d.finish = (long long *)(b + h->l.finish);
+    d.first = (long long *)(b + h->l.first);
     d.lo = (int *)(b + h->l.lo);
     d.hi = (int *)(b + h->l.hi);
     d.ex_prop = (unsigned long long *)(b + h->l.ex_prop);
@@ -561,6 +594,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     hipError_t e = hipMemsetAsync(h->base, 0, h->l.total, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.lnf, lnf.data(), H * 8, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.finish, fin.data(), H * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.first, fin.data(), H * 8, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.lo, lo.data(), H * 4, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.hi, hi.data(), H * 4, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && !J4.empty())
@@ -786,6 +820,100 @@ int rewl_get_window(rewl_ctx *h, int k, int64_t *lo, int64_t *hi, double *lnf, i
     return REWL_OK;
 }
 
+int rewl_get_first_merge(rewl_ctx *h, int64_t *out, int cap)
+{
+    if (!h || !out || cap < 0) return fail(REWL_EINVAL, "bad handle or output");
+    const int n = std::min(cap, h->p.n_windows);
+    std::vector<long long> f((size_t)h->p.n_windows);
+    int rc = d2h(h, f.data(), h->l.first, f.size());
+    if (rc) return rc;
+    for (int k = 0; k < n; ++k) out[k] = f[(size_t)k];
+    return REWL_OK;
+}
+
+int rewl_partition_balanced(int64_t n_bins, int n_windows, double overlap, int pre_windows,
+                            const int64_t *pre_lo, const int64_t *pre_hi,
+                            const int64_t *first_rounds, int64_t *lo, int64_t *hi)
+{
+    if (n_bins < 2 || n_windows < 1 || pre_windows < 1 || !(overlap > 0.0 && overlap < 1.0) ||
+        !pre_lo || !pre_hi || !first_rounds || !lo || !hi)
+        return fail(REWL_EINVAL, "bad arguments");
+    const std::vector<int64_t> plo(pre_lo, pre_lo + pre_windows), phi(pre_hi, pre_hi + pre_windows);
+    if (check_windows(n_bins, pre_windows, plo, phi)) return REWL_EINVAL;
+    for (int k = 0; k < pre_windows; ++k)
+        if (first_rounds[k] < 1) return fail(REWL_EINVAL, "first-iteration rounds must be >= 1");
+    // time density of each bin in the first iteration: the pre-run windows
+    // that hold the bin, each contributing its rounds per bin
+    std::vector<double> dens((size_t)n_bins);
+    for (int64_t b = 0; b < n_bins; ++b) {
+        double acc = 0.0;
+        int cover = 0;
+        for (int k = 0; k < pre_windows; ++k) {
+            if (b >= plo[k] && b <= phi[k]) {
+                acc = acc + (double)first_rounds[k] / (double)(phi[k] - plo[k] + 1);
+                ++cover;
+            }
+        }
+        dens[(size_t)b] = acc / (double)cover;
+    }
+    // bins as points of the time axis (trapezoids between neighbours)
+    std::vector<double> axis((size_t)n_bins);
+    axis[0] = 0.0;
+    for (int64_t b = 1; b < n_bins; ++b)
+        axis[(size_t)b] = axis[(size_t)b - 1] + (dens[(size_t)b - 1] + dens[(size_t)b]) * 0.5;
+    // the equal partition of that axis
+    const double width = axis[(size_t)n_bins - 1] / (1.0 + (double)(n_windows - 1) * (1.0 - overlap));
+    std::vector<int64_t> L((size_t)n_windows), H((size_t)n_windows);
+    int64_t first = 0, last = 0;
+    for (int k = 0; k < n_windows; ++k) {
+        const double start = ((double)k * (1.0 - overlap)) * width;
+        const double end = start + width;
+        while (first + 1 < n_bins && axis[(size_t)first + 1] <= start) ++first;
+        while (last < n_bins - 1 && axis[(size_t)last] < end) ++last;
+        L[(size_t)k] = first;
+        H[(size_t)k] = last;
+    }
+    H[(size_t)n_windows - 1] = n_bins - 1;
+    if (check_windows(n_bins, n_windows, L, H)) return REWL_EINVAL;
+    for (int k = 0; k < n_windows; ++k) {
+        lo[k] = L[(size_t)k];
+        hi[k] = H[(size_t)k];
+    }
+    return REWL_OK;
+}
+
+int rewl_jackknife(const double *lng, int runs, int64_t n_bins, double *mean, double *err)
+{
+    if (!lng || !mean || !err || runs < 2 || n_bins < 1) return fail(REWL_EINVAL, "bad arguments");
+    const double R = (double)runs;
+    std::vector<double> theta((size_t)runs);
+    for (int64_t b = 0; b < n_bins; ++b) {
+        bool seen = true;
+        double total = 0.0;
+        for (int r = 0; r < runs; ++r) {
+            const double x = lng[(size_t)r * (size_t)n_bins + (size_t)b];
+            seen = seen && std::isfinite(x);
+            total += x;
+        }
+        if (!seen) {
+            mean[b] = -HUGE_VAL;
+            err[b] = std::nan("");
+            continue;
+        }
+        double tbar = 0.0;
+        for (int r = 0; r < runs; ++r) {
+            theta[(size_t)r] = (total - lng[(size_t)r * (size_t)n_bins + (size_t)b]) / (R - 1.0);
+            tbar += theta[(size_t)r];
+        }
+        tbar /= R;
+        double ss = 0.0;
+        for (int r = 0; r < runs; ++r) ss += (theta[(size_t)r] - tbar) * (theta[(size_t)r] - tbar);
+        mean[b] = total / R;
+        err[b] = std::sqrt((R - 1.0) / R * ss);
+    }
+    return REWL_OK;
+}
+
 int rewl_get_walker(rewl_ctx *h, int w, int8_t *spins, int64_t *E, uint64_t *t, int *flat,
                     double *lng, uint32_t *H, uint8_t *visited)
 {
@@ -1003,6 +1131,7 @@ struct rewl_server {
         int64_t id;
         rewl_params p;
         std::vector<int8_t> couplings;
+        std::vector<int64_t> wlo, whi;  // windows (explicit or equal partition)
         size_t bytes;
     };
     std::vector<Pending> queue;         // FIFO
@@ -1128,6 +1257,8 @@ int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id)
     rewl_server::Pending q;
     q.id = s->next_id++;
     q.p = *p;
+    q.wlo = g.lo;
+    q.whi = g.hi;
     if (p->model == REWL_EA) {
         q.couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
         q.p.couplings = q.couplings.data();
@@ -1137,9 +1268,12 @@ int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id)
     q.bytes = layout(p, g).total;
     if (q.bytes > s->budget) return fail(REWL_EBUSY, "run larger than the server's device budget");
     s->queue.push_back(std::move(q));
-    // vector growth moved the couplings; point each entry at its own copy again
-    for (auto &e : s->queue)
+    // vector growth moved the copies; point each entry at its own again
+    for (auto &e : s->queue) {
         if (e.p.model == REWL_EA) e.p.couplings = e.couplings.data();
+        e.p.window_lo = e.wlo.data();
+        e.p.window_hi = e.whi.data();
+    }
     if (id) *id = s->queue.back().id;
     return REWL_OK;
 }

@@ -9,7 +9,8 @@
 //   H       nw x Wmax uint32 (window-local histogram of the current iteration)
 //   n_acc   nw uint64        (accepted sweep moves)
 //   lnf     h f64, done h int32, phase h int32 (1/t rule active), finish h
-//           int64, lo/hi h int32 (bins)
+//           int64, first h int64 (round of the first merge), lo/hi h int32
+//           (bins)
 //   ex_prop, ex_acc  h uint64 (exchange proposals / acceptances of pair (k,k+1))
 //   J4      N uint32         (EA: couplings to right, left, down, up neighbour,
 //                             one int8 each, packed little-endian)
@@ -43,6 +44,7 @@ struct RunDesc {
     int *done;
     int *phase;        // per window: 1 once it follows the 1/t rule
     long long *finish;
+    long long *first;  // per window: round of its first merge, -1 before
     int *lo, *hi;
     unsigned long long *ex_prop, *ex_acc;
     uint32_t *J4;

@@ -598,6 +598,7 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
     }
     if (tid == 0) {
         for (int s = 0; s < m; ++s) a.flat[k * m + s] = 0;
+        if (a.first[k] < 0) a.first[k] = round;
         const double Wt = (double)W / (double)a.t[k * m];  // the window's walkers share t
         double nl;
         if (one_over_t) {

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -55,3 +56,51 @@ def test_footprint_grows_with_walkers(rewl):
     a, _ = rewl.footprint(model="potts", L=64, q=10, n_windows=32, walkers_per_window=8)
     b, _ = rewl.footprint(model="potts", L=64, q=10, n_windows=32, walkers_per_window=4)
     assert a > b
+
+
+def test_balanced_partition_matches_oracle(oracle_lib):
+    """rewl_partition_balanced is host code: on random pre-runs it returns the
+    oracle's windows exactly, and refuses the same invalid cases."""
+    import paper_1305_5615_amd as rewl
+
+    rng = np.random.default_rng(11)
+    agree = 0
+    for _ in range(200):
+        B = int(rng.integers(20, 4000))
+        h = int(rng.integers(1, 40))
+        ph = int(rng.integers(1, 40))
+        o = float(rng.choice([0.5, 0.6, 0.75, 0.8]))
+        try:
+            plo, phi = oracle_lib.partition(B, ph, 0.75)
+        except ValueError:
+            continue
+        T = rng.integers(1, 10 ** 6, size=ph)
+        try:
+            want = oracle_lib.partition_balanced(B, h, o, plo, phi, T)
+        except ValueError:
+            want = None
+        try:
+            got = rewl.partition_balanced(B, h, o, plo, phi, T)
+        except rewl.RewlError:
+            got = None
+        assert (want is None) == (got is None), (B, h, ph, o)
+        if want is not None:
+            assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
+            agree += 1
+    assert agree > 100
+
+
+def test_jackknife_matches_oracle():
+    """rewl_jackknife (host code) against the oracle's definition."""
+    import paper_1305_5615_amd as rewl
+    from oracle.errors import jackknife
+
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(6, 300)) * 0.05 + np.linspace(0, 700, 300)
+    x[2, 5] = -np.inf
+    m1, e1 = jackknife(x)
+    m2, e2 = rewl.jackknife(x)
+    fin = np.isfinite(m1)
+    assert np.array_equal(fin, np.isfinite(m2)) and np.isnan(e2[5])
+    assert np.allclose(m1[fin], m2[fin], rtol=1e-14, atol=0)
+    assert np.allclose(e1[fin], e2[fin], rtol=1e-9, atol=1e-13)

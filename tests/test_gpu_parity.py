@@ -143,6 +143,45 @@ def test_one_over_t_rounds_bitexact(gpu, orc, name, kw, steps):
     assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
 
 
+@pytest.mark.parametrize("model,L,q", [("ising", 8, 2), ("potts", 6, 4)])
+def test_balanced_partition_run_bitexact(gpu, orc, model, L, q):
+    """Run-time balanced windows: the pre-run's first-merge rounds agree with
+    the oracle's, both derive the same windows, and the run on them is
+    bit-exact with the oracle to convergence, stitched ln g included."""
+    kw = dict(model=model, L=L, q=q, n_windows=4, walkers_per_window=2, S=1500,
+              lnf_final=1e-3, seed=12)
+    g, o = _pair(gpu, orc, **kw)
+    for _ in range(2000):
+        if (o.first_merge() >= 0).all():
+            break
+        g.step(4)
+        o.step(4)
+    f = o.first_merge()
+    assert (f >= 0).all()
+    assert np.array_equal(g.first_merge(), f)
+    plo = np.array([w["lo"] for w in o.windows()])
+    phi = np.array([w["hi"] for w in o.windows()])
+    want = orc.partition_balanced(o.n_bins, 4, 0.75, plo, phi, f + 1)
+    got = gpu.partition_balanced(g.n_bins, 4, 0.75, plo, phi, f + 1)
+    assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
+    lo, hi, _ = gpu.balanced_windows(chunk=4, **kw)
+    assert np.array_equal(lo, want[0]) and np.array_equal(hi, want[1])
+    print("balanced windows:", list(zip(lo, hi)), flush=True)
+    gb, ob = _pair(gpu, orc, windows=(lo, hi), **kw)
+    assert_same_state(gb, ob, "balanced start-up")
+    for rounds in (1, 10, 60):
+        gb.step(rounds)
+        ob.step(rounds)
+        assert_same_state(gb, ob, f"balanced after {rounds}")
+    ok_g, _ = gb.run()
+    assert ok_g and ob.run()
+    assert_same_state(gb, ob, "balanced converged")
+    lg, lo_ = gb.lng(), ob.lng()
+    fin = np.isfinite(lo_)
+    assert np.array_equal(np.isfinite(lg), fin)
+    assert np.array_equal(lg[fin].view(np.uint64), lo_[fin].view(np.uint64))
+
+
 def test_ising8_full_run_bitexact(gpu, orc):
     """The small Ising workload run to convergence: same rounds, same stitched ln g."""
     p = run_params("ising8", seed=2)

@@ -200,6 +200,92 @@ def test_partition_invariants(oracle_lib):
 
 
 # ---------------------------------------------------------- exact DOS tools --
+def test_balanced_partition_uniform_is_equal(oracle_lib):
+    """With first-iteration time proportional to window width (a uniform time
+    density) the run-time balanced partition is the equal partition, exactly."""
+    for B, h, o in [(65, 4, 0.75), (1025, 16, 0.75), (8193, 32, 0.75), (577, 8, 0.6),
+                    (300, 7, 0.5)]:
+        lo, hi = oracle_lib.partition(B, h, o)
+        lo2, hi2 = oracle_lib.partition_balanced(B, h, o, lo, hi, hi - lo + 1)
+        assert np.array_equal(lo, lo2) and np.array_equal(hi, hi2), (B, h, o)
+
+
+def test_balanced_partition_equalises_time(oracle_lib):
+    """A pre-run whose low windows took 9x longer per bin: the balanced windows
+    are narrower there, and every window holds the same first-iteration time
+    up to the density of one bin at each end."""
+    B, h, o = 1025, 16, 0.75
+    plo, phi = oracle_lib.partition(B, h, o)
+    T = np.where(np.arange(h) < h // 2, 9, 1) * (phi - plo + 1)
+    lo, hi = oracle_lib.partition_balanced(B, h, o, plo, phi, T)
+    assert lo[0] == 0 and hi[-1] == B - 1
+    assert np.all(np.diff(lo) > 0) and np.all(np.diff(hi) > 0)
+    # the time density the partition sees, rebuilt from its definition
+    t = np.zeros(B)
+    for b in range(B):
+        ks = [k for k in range(h) if plo[k] <= b <= phi[k]]
+        t[b] = np.mean([T[k] / (phi[k] - plo[k] + 1) for k in ks])
+    F = np.concatenate([[0.0], np.cumsum((t[:-1] + t[1:]) / 2)])
+    w = F[-1] / (1 + (h - 1) * (1 - o))
+    spans = F[hi] - F[lo]
+    assert np.all(np.abs(spans[:-1] - w) <= 2 * t.max() + 1e-9), (spans, w)
+    widths = hi - lo + 1
+    assert widths[-1] > 3 * widths[0] and widths[-2] > 2 * widths[0]
+
+
+def test_first_merge_round(oracle_lib):
+    """The round of each window's first merge is the round in which its ln f
+    first dropped below ln f_init."""
+    run = oracle_lib.Run("ising", 6, n_windows=3, walkers_per_window=2, S=500, seed=3,
+                         lnf_final=0.1)
+    seen = [-1] * 3
+    for r in range(2000):
+        run.step(1)
+        for k in range(3):
+            if seen[k] < 0 and run.window(k)["lnf"] < 1.0:
+                seen[k] = r
+        if min(seen) >= 0:
+            break
+    assert list(run.first_merge()) == seen
+
+
+def test_explicit_windows_match_equal_partition(oracle_lib):
+    """A run given the equal partition explicitly evolves exactly as the
+    default run; an invalid explicit partition is refused."""
+    lo, hi = oracle_lib.partition(65, 4, 0.75)
+    a = oracle_lib.Run("ising", 8, n_windows=4, walkers_per_window=2, S=700, seed=5)
+    b = oracle_lib.Run("ising", 8, n_windows=4, walkers_per_window=2, S=700, seed=5,
+                       windows=(lo, hi))
+    a.step(20)
+    b.step(20)
+    for w in range(8):
+        x, y = a.walker(w), b.walker(w)
+        assert np.array_equal(x["lng"], y["lng"]) and np.array_equal(x["spins"], y["spins"])
+    bad_hi = hi.copy()
+    bad_hi[1] = lo[2]          # windows 1 and 2 would share one bin
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ising", 8, n_windows=4, windows=(lo, bad_hi))
+
+
+def test_jackknife_identities():
+    """The jackknife error of a mean is the standard error of the mean,
+    s / sqrt(R) with the unbiased s (an identity); two runs give |a - b| / 2;
+    equal runs give 0; a bin some run never visited gives -inf and NaN."""
+    from oracle.errors import jackknife
+
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(9, 40)) * 3 + 100
+    mean, err = jackknife(x)
+    assert np.allclose(mean, x.mean(0), rtol=0, atol=1e-12)
+    assert np.allclose(err, x.std(0, ddof=1) / 3.0, rtol=1e-12, atol=0)
+    two = np.array([[1.0, 5.0], [4.0, 5.0]])
+    m2, e2 = jackknife(two)
+    assert np.allclose(e2, [1.5, 0.0], atol=1e-15)
+    x[3, 7] = -np.inf
+    m3, e3 = jackknife(x)
+    assert m3[7] == -np.inf and np.isnan(e3[7]) and np.isfinite(e3[8])
+
+
 def test_exact_ising_three_ways():
     """Kaufman's closed form = transfer matrix = enumeration (L = 4); L = 6 = transfer."""
     from oracle import exact
