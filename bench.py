@@ -44,8 +44,9 @@ sys.path.insert(0, ROOT)
 
 # VALU lane-slots one sweep attempt needs (Ising; quarter-rate 32-bit
 # multiplies count 4): Philox4x32-10 100, site draw 4, ln u 50, neighbours 20,
-# the accept/update chain 20.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_SLOTS_PER_ATTEMPT = {"ising": 194, "ea": 200, "potts": 204}
+# the accept/update chain 20; the glasses add the coupling terms, the 3D one
+# two more neighbours.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_SLOTS_PER_ATTEMPT = {"ising": 194, "ea": 200, "potts": 204, "ea3": 212}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOAD_TEXT = {
@@ -57,6 +58,8 @@ WORKLOAD_TEXT = {
                "ln f 1 -> 1e-8, 1e4 attempts/walker/round",
     "ea24": "2D +-J EA glass L=24 periodic, 8 windows x 4 walkers, overlap 0.75, flatness 0.8, "
             "ln f 1 -> 1e-6, 1e4 attempts/walker/round",
+    "ea3d12": "3D +-J EA glass 12x12x12 periodic, 8 windows x 4 walkers, overlap 0.75, "
+              "flatness 0.8, ln f 1 -> 1e-6, 1e4 attempts/walker/round",
 }
 
 

@@ -52,7 +52,11 @@ enum {
     REWL_ESTITCH = -7   /* a window overlap holds no commonly visited bin */
 };
 
-enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2 };
+/* Models (the paper's tests: 2D Ising, 2D q-state Potts, +-J spin glasses).
+ * REWL_ISING, REWL_POTTS, REWL_EA live on the L x L torus (N = L^2 sites,
+ * 2N bonds); REWL_EA3 is the +-J glass on the L x L x L torus (N = L^3
+ * sites, 3N bonds, the paper's 12^3 ground-state test). */
+enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2, REWL_EA3 = 3 };
 
 /* ln f schedules.  REWL_HALVING: ln f halves at every merge (f -> sqrt f).
  * REWL_ONE_OVER_T: halving until a halving would take ln f below W/t (W bins
@@ -63,17 +67,20 @@ enum { REWL_ISING = 0, REWL_POTTS = 1, REWL_EA = 2 };
 enum { REWL_HALVING = 0, REWL_ONE_OVER_T = 1 };
 
 /* Parameters of one run.
- *  couplings: REWL_EA only, 2*L*L values +-1, [2i] = J(i, right neighbour),
- *             [2i+1] = J(i, lower neighbour), site i = row*L + column; else NULL.
- *  e_min, e_max: inclusive energy range; clipped to the model's range and, for
- *             REWL_EA, aligned inwards onto the energy class -2N + 2 n_neg (mod 4)
- *             of the couplings.
+ *  couplings: REWL_EA: 2*L*L values +-1, [2i] = J(i, right neighbour),
+ *             [2i+1] = J(i, lower neighbour), site i = row*L + column;
+ *             REWL_EA3: 3*L^3 values, [3i + a] = J(i, next site along axis a),
+ *             a = x, y, z, site i = (z L + y) L + x; else NULL.
+ *  e_min, e_max: inclusive energy range; clipped to the model's range
+ *             ([-2N, 2N], Potts [-2N, 0], 3D [-3N, 3N]) and, for the glasses,
+ *             aligned inwards onto the energy class -B + 2 n_neg (mod 4) of the
+ *             couplings (B bonds, n_neg of them -1).
  *  n_windows >= 1, 0 < overlap < 1, walkers_per_window in [1, 64],
  *  0 < flatness <= 1, lnf_init > 0, lnf_final > 0,
  *  attempts_per_round >= 1 (attempts per walker between exchange steps),
  *  seed: Philox4x32-10 key, schedule: REWL_HALVING or REWL_ONE_OVER_T.
- *  Windows narrower than 2 bins, overlaps below 2 bins, 3 > L or L > 256,
- *  q outside [2, 127] (Potts) are REWL_EINVAL. */
+ *  Windows narrower than 2 bins, overlaps below 2 bins, 3 > L or L > 256
+ *  (REWL_EA3: 2 > L or L > 32), q outside [2, 127] (Potts) are REWL_EINVAL. */
 typedef struct rewl_params {
     int model;
     int L;

@@ -14,7 +14,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rewl_oracle.c")
 LIB = os.path.join(HERE, "librewl_oracle.so")
 
-MODELS = {"ising": 0, "potts": 1, "ea": 2}
+MODELS = {"ising": 0, "potts": 1, "ea": 2, "ea3": 3}
+
+
+def n_sites(model, L):
+    return L ** 3 if model == "ea3" else L * L
+
+
+def bonds_per_site(model):
+    return 3 if model == "ea3" else 2
 SCHEDULES = {"halving": 0, "1/t": 1}
 
 
@@ -144,11 +152,12 @@ class Run:
                  overlap=0.75, walkers_per_window=2, flatness=0.8, lnf_init=1.0,
                  lnf_final=1e-6, S=10_000, seed=1, n_threads=1, schedule="halving",
                  windows=None):
-        N = L * L
+        N = n_sites(model, L)
+        nb = bonds_per_site(model)
         if e_min is None:
-            e_min = -2 * N
+            e_min = -nb * N
         if e_max is None:
-            e_max = 0 if model == "potts" else 2 * N
+            e_max = 0 if model == "potts" else nb * N
         J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
         wl = wh = None
         if windows is not None:

@@ -4,7 +4,8 @@ These are the truth sources the oracle is pinned against (the paper compares its
 2D Ising results with exact ones, in the paragraph on the Ising and Potts tests):
 
 * ``brute_dos``: enumeration of every configuration (Ising, q-state Potts and
-  +-J models on L x L tori with at most a few million states).
+  +-J models on L x L tori, and the +-J model on L x L x L tori, with at most a
+  few tens of millions of states).
 * ``ising_dos_transfer``: the 2D Ising DOS on an L x L torus by a row-to-row
   transfer matrix over polynomials in the number of unsatisfied bonds, in exact
   integer arithmetic (independent of the closed form below).
@@ -31,29 +32,47 @@ def _bonds(L):
     return idx.ravel(), right, down
 
 
+def _bonds3(L):
+    """(site, +x, +y, +z neighbour) index arrays on the L^3 torus, sites
+    i = (z L + y) L + x."""
+    idx = np.arange(L ** 3).reshape(L, L, L)  # [z, y, x]
+    return (idx.ravel(), np.roll(idx, -1, axis=2).ravel(), np.roll(idx, -1, axis=1).ravel(),
+            np.roll(idx, -1, axis=0).ravel())
+
+
 def brute_dos(model, L, q=2, couplings=None):
     """Exact DOS by enumerating all configurations.
 
-    model: 'ising' | 'potts' | 'ea'.  couplings (ea): int8 array of 2N values,
-    [2i] = J(i, right), [2i+1] = J(i, down).  Returns a dict {E: count}.
+    model: 'ising' | 'potts' | 'ea' | 'ea3'.  couplings (ea): int8 array of 2N
+    values, [2i] = J(i, right), [2i+1] = J(i, down); (ea3): 3N values,
+    [3i + a] = J(i, next site along axis a = x, y, z).  Returns a dict
+    {E: count}.
     """
-    N = L * L
-    nstates = 2 if model in ("ising", "ea") else q
-    total = nstates ** N
-    if total > 50_000_000:
+    N = L ** 3 if model == "ea3" else L * L
+    nstates = 2 if model in ("ising", "ea", "ea3") else q
+    # +-1 models: E is even under flipping every spin, so the last spin is held
+    # at +1 and every count doubled
+    half = nstates == 2
+    total = nstates ** (N - 1) if half else nstates ** N
+    if total > 80_000_000:
         raise ValueError("too many states for enumeration")
     site, right, down = _bonds(L)
     if model == "ea":
         J = np.asarray(couplings, dtype=np.int64).reshape(N, 2)
+    if model == "ea3":
+        site, xp, yp, zp = _bonds3(L)
+        J = np.asarray(couplings, dtype=np.int64).reshape(N, 3)
     counts = {}
     chunk = 1 << 20
     for start in range(0, total, chunk):
         codes = np.arange(start, min(total, start + chunk), dtype=np.int64)
         digits = np.empty((codes.size, N), dtype=np.int64)
         c = codes.copy()
-        for i in range(N):
+        for i in range(N - 1 if half else N):
             digits[:, i] = c % nstates
             c //= nstates
+        if half:
+            digits[:, N - 1] = 1
         if model == "potts":
             E = -((digits[:, site] == digits[:, right]).sum(1)
                   + (digits[:, site] == digits[:, down]).sum(1))
@@ -61,12 +80,16 @@ def brute_dos(model, L, q=2, couplings=None):
             s = 2 * digits - 1
             if model == "ising":
                 E = -((s[:, site] * s[:, right]).sum(1) + (s[:, site] * s[:, down]).sum(1))
+            elif model == "ea3":
+                E = -((J[:, 0] * s[:, site] * s[:, xp]).sum(1)
+                      + (J[:, 1] * s[:, site] * s[:, yp]).sum(1)
+                      + (J[:, 2] * s[:, site] * s[:, zp]).sum(1))
             else:
                 E = -((J[:, 0] * s[:, site] * s[:, right]).sum(1)
                       + (J[:, 1] * s[:, site] * s[:, down]).sum(1))
         vals, cnt = np.unique(E, return_counts=True)
         for v, n in zip(vals.tolist(), cnt.tolist()):
-            counts[v] = counts.get(v, 0) + n
+            counts[v] = counts.get(v, 0) + (2 * n if half else n)
     return counts
 
 

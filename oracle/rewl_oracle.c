@@ -138,18 +138,38 @@ double orc_ln_u(double u)
  * Sites i = r L + c on an L x L torus.  Ising: E = -sum_<ij> s_i s_j;
  * Potts: E = -sum_<ij> delta(s_i, s_j); +-J (Edwards-Anderson):
  * E = -sum_<ij> J_ij s_i s_j.  Each bond is counted once through the right and
- * lower neighbour of every site. */
+ * lower neighbour of every site.  The 3D +-J model (the paper's 12^3 spin-glass
+ * test) lives on an L x L x L torus, sites i = (z L + y) L + x, with couplings
+ * J[3i] to +x, J[3i+1] to +y and J[3i+2] to +z. */
 static int right_of(int i, int L) { int r = i / L, c = i % L; return r * L + (c + 1) % L; }
 static int left_of(int i, int L)  { int r = i / L, c = i % L; return r * L + (c + L - 1) % L; }
 static int down_of(int i, int L)  { int r = i / L, c = i % L; return ((r + 1) % L) * L + c; }
 static int up_of(int i, int L)    { int r = i / L, c = i % L; return ((r + L - 1) % L) * L + c; }
 
+/* neighbour of site i one step along axis a (0: x, 1: y, 2: z) in direction
+ * d (+1 or -1) on the L^3 torus */
+static int nb3(int i, int L, int a, int d)
+{
+    int x = i % L, y = (i / L) % L, z = i / (L * L);
+    if (a == 0) x = (x + d + L) % L;
+    else if (a == 1) y = (y + d + L) % L;
+    else z = (z + d + L) % L;
+    return (z * L + y) * L + x;
+}
+
+int orc_sites(int model, int L) { return model == ORC_EA3 ? L * L * L : L * L; }
+
 int64_t orc_energy(int model, int L, int q, const int8_t *s, const int8_t *J)
 {
     (void)q;
-    int N = L * L;
+    int N = orc_sites(model, L);
     int64_t E = 0;
     for (int i = 0; i < N; ++i) {
+        if (model == ORC_EA3) {
+            for (int a = 0; a < 3; ++a)
+                E -= (int64_t)J[3 * i + a] * s[i] * s[nb3(i, L, a, +1)];
+            continue;
+        }
         int rt = right_of(i, L), dn = down_of(i, L);
         if (model == ORC_ISING) {
             E -= (int64_t)s[i] * s[rt] + (int64_t)s[i] * s[dn];
@@ -165,6 +185,14 @@ int64_t orc_energy(int model, int L, int q, const int8_t *s, const int8_t *J)
 /* energy change when site i goes from s[i] to `nw` */
 static int64_t delta_e(int model, int L, const int8_t *s, const int8_t *J, int i, int nw)
 {
+    if (model == ORC_EA3) {
+        int64_t h = 0;
+        for (int a = 0; a < 3; ++a) {
+            int up = nb3(i, L, a, +1), dn = nb3(i, L, a, -1);
+            h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * dn + a] * s[dn];
+        }
+        return 2 * (int64_t)s[i] * h;
+    }
     int rt = right_of(i, L), lf = left_of(i, L), dn = down_of(i, L), up = up_of(i, L);
     if (model == ORC_ISING)
         return 2 * (int64_t)s[i] * (s[rt] + s[lf] + s[dn] + s[up]);
@@ -340,7 +368,7 @@ static int init_walker(orc_run *run, int w)
     uint64_t d = 0;
     while (dist_to_window(run, k, E) > 0) {
         if (d == (uint64_t)cap) {
-            if (run->model == ORC_EA) return -4;
+            if (run->model == ORC_EA || run->model == ORC_EA3) return -4;
             for (int i = 0; i < N; ++i) s[i] = (run->model == ORC_POTTS) ? 0 : 1;
             E = orc_energy(run->model, run->L, run->q, s, run->J);
         }
@@ -367,22 +395,24 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
                int schedule, const int64_t *win_lo, const int64_t *win_hi)
 {
     *out = NULL;
-    if (model < 0 || model > 2 || L < 3 || L > 256 || h < 1 || m < 1 || S < 1) return -1;
+    if (model < 0 || model > 3 || L > 256 || h < 1 || m < 1 || S < 1) return -1;
+    if (model == ORC_EA3 ? (L < 2 || L > 32) : L < 3) return -1;
     if (model == ORC_POTTS && (q < 2 || q > 127)) return -1;
-    if (model == ORC_EA && !couplings) return -1;
+    if ((model == ORC_EA || model == ORC_EA3) && !couplings) return -1;
     if (!(p > 0.0 && p <= 1.0) || !(lnf_final > 0.0) || !(lnf_init > 0.0)) return -1;
     if (schedule != 0 && schedule != 1) return -1;
-    int N = L * L;
+    int N = orc_sites(model, L);
+    int bonds = (model == ORC_EA3) ? 3 : 2;   /* bonds per site */
     int64_t step = (model == ORC_POTTS) ? 1 : 4;
-    int64_t lo_full = -2 * (int64_t)N, hi_full = (model == ORC_POTTS) ? 0 : 2 * (int64_t)N;
+    int64_t lo_full = -(int64_t)bonds * N, hi_full = (model == ORC_POTTS) ? 0 : (int64_t)bonds * N;
     int64_t cls = 0; /* energies lie on cls + step Z */
-    if (model == ORC_EA) {
+    if (model == ORC_EA || model == ORC_EA3) {
         int64_t n_neg = 0;
-        for (int i = 0; i < 2 * N; ++i) {
+        for (int i = 0; i < bonds * N; ++i) {
             if (couplings[i] != 1 && couplings[i] != -1) return -1;
             n_neg += couplings[i] < 0;
         }
-        cls = -2 * (int64_t)N + 2 * n_neg;
+        cls = -(int64_t)bonds * N + 2 * n_neg;
     } else if (model == ORC_ISING) {
         cls = -2 * (int64_t)N;
     }
@@ -416,7 +446,7 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->Wmax = 0;
     for (int k = 0; k < h; ++k) if (wsize(run, k) > run->Wmax) run->Wmax = wsize(run, k);
     size_t nw = (size_t)run->nw;
-    run->J = calloc(2 * (size_t)N, 1);
+    run->J = calloc((size_t)bonds * N, 1);
     run->lnf = calloc(h, sizeof(double)); run->done = calloc(h, sizeof(int));
     run->phase = calloc(h, sizeof(int));
     run->finish = calloc(h, sizeof(int64_t));
@@ -433,7 +463,7 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
         orc_destroy(run);
         return -2;
     }
-    if (model == ORC_EA) memcpy(run->J, couplings, 2 * (size_t)N);
+    if (model == ORC_EA || model == ORC_EA3) memcpy(run->J, couplings, (size_t)bonds * N);
     for (int k = 0; k < h; ++k) { run->lnf[k] = lnf_init; run->finish[k] = -1; run->first[k] = -1; }
     for (int w = 0; w < run->nw; ++w) {
         int rc = init_walker(run, w);
@@ -780,10 +810,11 @@ int orc_get_lng(orc_run *run, double *out, int64_t cap)
     if (rc) return rc;
     int64_t N = run->N;
     double ref = 0.0, target = 0.0;
-    if (run->model != ORC_EA && run->full_lo && isfinite(out[0])) {
+    int glass = run->model == ORC_EA || run->model == ORC_EA3;
+    if (!glass && run->full_lo && isfinite(out[0])) {
         ref = out[0];
         target = log(run->model == ORC_POTTS ? (double)run->q : 2.0);
-    } else if (run->model == ORC_EA && run->full_lo && run->full_hi) {
+    } else if (glass && run->full_lo && run->full_hi) {
         double mx = -INFINITY;
         for (int64_t b = 0; b < run->B; ++b) if (out[b] > mx) mx = out[b];
         double sum = 0.0;

@@ -20,12 +20,14 @@
 #define ORC_ISING 0
 #define ORC_POTTS 1
 #define ORC_EA 2
+#define ORC_EA3 3   /* +-J glass on the L x L x L torus */
 
 typedef struct orc_run orc_run;
 
 /* Create a run.  couplings: EA only, 2*L*L int8 values +-1, interleaved per
  * site i as [2i] = J(i, right neighbour), [2i+1] = J(i, lower neighbour);
- * copied.  e_min/e_max are inclusive; for EA they are aligned inwards onto the
+ * EA3: 3*L^3 values, [3i + a] = J(i, next site along axis a = x, y, z), sites
+ * i = (z L + y) L + x, 2 <= L <= 32 (L >= 3 for the 2D models); copied.  e_min/e_max are inclusive; for EA they are aligned inwards onto the
  * energy class of the couplings.  lnf_init is the first ln f; S the number of
  * attempts per walker per round; n_threads the OpenMP threads used by the
  * sweep (0 = runtime default); schedule 0 halves ln f at every merge, 1 halves
@@ -71,6 +73,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 double orc_ln_u(double u);
 double orc_uniform(uint32_t hi, uint32_t lo);
 int64_t orc_energy(int model, int L, int q, const int8_t *spins, const int8_t *couplings);
+int orc_sites(int model, int L);
 int orc_partition(int64_t n_bins, int n_windows, double overlap, int64_t *lo, int64_t *hi);
 /* Run-time balanced partition from a pre-run's windows and first-iteration
  * rounds T (see rewl_oracle.c). */

@@ -16,7 +16,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "librewl.so")
 
-MODELS = {"ising": 0, "potts": 1, "ea": 2}
+MODELS = {"ising": 0, "potts": 1, "ea": 2, "ea3": 3}
+
+
+def n_sites(model, L):
+    """Sites of the lattice: L^2, or L^3 for the 3D glass."""
+    return L ** 3 if model == "ea3" else L * L
 ERRORS = {1: "REWL_NOT_CONVERGED", -1: "REWL_EINVAL", -2: "REWL_ENOMEM", -3: "REWL_EDEVICE",
           -4: "REWL_EINIT", -5: "REWL_ECORRUPT", -6: "REWL_EBUSY", -7: "REWL_ESTITCH"}
 
@@ -112,11 +117,12 @@ def make_params(model, L, q=2, couplings=None, e_min=None, e_max=None, n_windows
     """rewl_params for the arguments, and the arrays it points to (keep them
     alive until the library has copied them).  windows: (lo, hi) bin arrays of
     an explicit partition, or None for the equal partition."""
-    N = L * L
+    N = n_sites(model, L)
+    nb = 3 if model == "ea3" else 2
     if e_min is None:
-        e_min = -2 * N
+        e_min = -nb * N
     if e_max is None:
-        e_max = 0 if model == "potts" else 2 * N
+        e_max = 0 if model == "potts" else nb * N
     J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
     wl = wh = None
     if windows is not None:
@@ -196,7 +202,7 @@ class RunView:
 
     def _attach(self, h, model, L, params):
         self._h = h
-        self.model, self.L, self.N = model, L, L * L
+        self.model, self.L, self.N = model, L, n_sites(model, L)
         self.params = params
         info = self.info()
         self.n_bins, self.e_min, self.e_step = info["n_bins"], info["e_min"], info["e_step"]

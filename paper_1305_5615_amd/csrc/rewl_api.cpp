@@ -40,6 +40,9 @@ int hip_fail(hipError_t e, const char *what)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// bonds per site: 2 on the square lattice, 3 on the cubic one
+int bonds_per_site(int model) { return model == REWL_EA3 ? 3 : 2; }
+
 // Geometry of a run derived from its parameters.
 struct Geometry {
     int N = 0, step = 0, nw = 0, Npad = 0, Wmax = 0;
@@ -97,8 +100,9 @@ int check_windows(int64_t B, int n, const std::vector<int64_t> &lo, const std::v
 int validate(const rewl_params *p, Geometry &g)
 {
     if (!p) return fail(REWL_EINVAL, "params is NULL");
-    if (p->model < 0 || p->model > 2) return fail(REWL_EINVAL, "unknown model");
-    if (p->L < 3 || p->L > 256) return fail(REWL_EINVAL, "L must be in [3, 256]");
+    if (p->model < 0 || p->model > 3) return fail(REWL_EINVAL, "unknown model");
+    if (p->model == REWL_EA3 ? (p->L < 2 || p->L > 32) : (p->L < 3 || p->L > 256))
+        return fail(REWL_EINVAL, "L must be in [3, 256] (3D glass: [2, 32])");
     if (p->model == REWL_POTTS && (p->q < 2 || p->q > 127))
         return fail(REWL_EINVAL, "q must be in [2, 127]");
     if (p->n_windows < 1) return fail(REWL_EINVAL, "n_windows must be >= 1");
@@ -111,20 +115,21 @@ int validate(const rewl_params *p, Geometry &g)
     if (p->attempts_per_round < 1) return fail(REWL_EINVAL, "attempts_per_round must be >= 1");
     if (p->schedule != REWL_HALVING && p->schedule != REWL_ONE_OVER_T)
         return fail(REWL_EINVAL, "unknown ln f schedule");
-    const int64_t N = (int64_t)p->L * p->L;
+    const int64_t N = (int64_t)p->L * p->L * (p->model == REWL_EA3 ? p->L : 1);
+    const int64_t nb = bonds_per_site(p->model);
     g.N = (int)N;
     g.step = (p->model == REWL_POTTS) ? 1 : 4;
-    const int64_t lo_full = -2 * N, hi_full = (p->model == REWL_POTTS) ? 0 : 2 * N;
+    const int64_t lo_full = -nb * N, hi_full = (p->model == REWL_POTTS) ? 0 : nb * N;
     int64_t cls = 0;
-    if (p->model == REWL_EA) {
-        if (!p->couplings) return fail(REWL_EINVAL, "EA model needs couplings");
+    if (p->model == REWL_EA || p->model == REWL_EA3) {
+        if (!p->couplings) return fail(REWL_EINVAL, "the glass models need couplings");
         int64_t n_neg = 0;
-        for (int64_t i = 0; i < 2 * N; ++i) {
+        for (int64_t i = 0; i < nb * N; ++i) {
             const int8_t c = p->couplings[i];
             if (c != 1 && c != -1) return fail(REWL_EINVAL, "couplings must be +-1");
             n_neg += c < 0;
         }
-        cls = -2 * N + 2 * n_neg;
+        cls = -nb * N + 2 * n_neg;
     } else if (p->model == REWL_ISING) {
         cls = -2 * N;
     }
@@ -158,7 +163,7 @@ int validate(const rewl_params *p, Geometry &g)
         g.Wmax = std::max<int>(g.Wmax, (int)(g.hi[k] - g.lo[k] + 1));
     g.nw = p->n_windows * p->walkers_per_window;
     g.Npad = (int)align_up((size_t)N, 16);
-    if (sweep_lds_bytes(1, g.Wmax, g.N, p->model == REWL_EA) > kMaxLds)
+    if (sweep_lds_bytes(1, g.Wmax, g.N, model_j_words(p->model)) > kMaxLds)
         return fail(REWL_EINVAL, "one walker's window does not fit the LDS of a CU");
     return REWL_OK;
 }
@@ -195,7 +200,7 @@ Layout layout(const rewl_params *p, const Geometry &g)
     l.hi = take(h * 4);
     l.ex_prop = take(h * 8);
     l.ex_acc = take(h * 8);
-    l.J4 = take(p->model == REWL_EA ? (size_t)g.N * 4 : 4);
+    l.J4 = take(std::max<size_t>(4, (size_t)model_j_words(p->model) * 4 * (size_t)g.N));
     l.round = take(8);
     l.status = take(4);
     l.total = off;
@@ -304,7 +309,7 @@ int rebuild(rewl_batch *b)
     std::vector<RunDesc> descs;
     std::vector<SweepItem> sweep;
     std::vector<WinItem> win, pair;
-    int max_N = 1, max_W = 1, any_ea = 0;
+    int max_N = 1, max_W = 1, j_words = 0;
     for (size_t i = 0; i < b->runs.size(); ++i) {
         rewl_ctx *r = b->runs[i];
         if (!r) continue;
@@ -316,9 +321,9 @@ int rebuild(rewl_batch *b)
         for (int k = 0; k < r->p.n_windows / 2; ++k) pair.push_back(WinItem{idx, k});
         max_N = std::max(max_N, r->g.N);
         max_W = std::max(max_W, r->g.Wmax);
-        any_ea |= r->p.model == REWL_EA;
+        j_words = std::max(j_words, model_j_words(r->p.model));
     }
-    if (sweep_lds_bytes(b->P, max_W, max_N, any_ea != 0) > kMaxLds)
+    if (sweep_lds_bytes(b->P, max_W, max_N, j_words) > kMaxLds)
         return fail(REWL_EINVAL, "walkers_per_wave too large for these runs' LDS footprint");
     const size_t n_runs = descs.size();
     size_t off = 0;
@@ -358,7 +363,7 @@ int rebuild(rewl_batch *b)
     d.P = b->P;
     d.max_N = max_N;
     d.max_W = max_W;
-    d.any_ea = any_ea;
+    d.j_words = j_words;
     d.region = (int)sweep_region(max_W, max_N, kWave / b->P);
     b->done_d = (int *)(t + o_done);
     if (b->pinned_cap < std::max<size_t>(n_runs, 1)) {
@@ -513,8 +518,9 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     // the windows live in the geometry from here on
     h->p.window_lo = h->g.lo.data();
     h->p.window_hi = h->g.hi.data();
-    if (p->model == REWL_EA) {
-        h->couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
+    if (p->model == REWL_EA || p->model == REWL_EA3) {
+        h->couplings.assign(p->couplings,
+                            p->couplings + (size_t)bonds_per_site(p->model) * (size_t)g.N);
         h->p.couplings = h->couplings.data();
     } else {
         h->p.couplings = nullptr;
@@ -546,6 +552,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     d.e_min = (int)g.e_min;
     d.step = g.step;
     d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
+    d.l2_magic = (uint32_t)(((uint64_t)1 << 32) / ((uint64_t)p->L * (uint64_t)p->L) + 1);
     d.key0 = (uint32_t)p->seed;
     d.key1 = (uint32_t)(p->seed >> 32);
     d.S = p->attempts_per_round;
@@ -590,6 +597,22 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
             J4[i] = (uint32_t)(uint8_t)J[2 * i] | ((uint32_t)(uint8_t)J[2 * lf] << 8) |
                     ((uint32_t)(uint8_t)J[2 * i + 1] << 16) | ((uint32_t)(uint8_t)J[2 * up + 1] << 24);
         }
+    } else if (p->model == REWL_EA3) {
+        // two words per site: +x, -x, +y, -y | +z, -z (bond a of site i is J[3i + a])
+        J4.resize(2 * (size_t)N);
+        const int8_t *J = h->p.couplings;
+        const int L2 = L * L;
+        for (int i = 0; i < N; ++i) {
+            const int x = i % L, y = (i / L) % L, z = i / L2;
+            const int xm = i - x + (x + L - 1) % L;
+            const int ym = z * L2 + ((y + L - 1) % L) * L + x;
+            const int zm = ((z + L - 1) % L) * L2 + y * L + x;
+            J4[2 * (size_t)i] = (uint32_t)(uint8_t)J[3 * i] | ((uint32_t)(uint8_t)J[3 * xm] << 8) |
+                                ((uint32_t)(uint8_t)J[3 * i + 1] << 16) |
+                                ((uint32_t)(uint8_t)J[3 * ym + 1] << 24);
+            J4[2 * (size_t)i + 1] = (uint32_t)(uint8_t)J[3 * i + 2] |
+                                    ((uint32_t)(uint8_t)J[3 * zm + 2] << 8);
+        }
     }
     hipError_t e = hipMemsetAsync(h->base, 0, h->l.total, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.lnf, lnf.data(), H * 8, hipMemcpyHostToDevice, stream);
@@ -598,7 +621,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     if (e == hipSuccess) e = hipMemcpyAsync(d.lo, lo.data(), H * 4, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.hi, hi.data(), H * 4, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && !J4.empty())
-        e = hipMemcpyAsync(d.J4, J4.data(), (size_t)N * 4, hipMemcpyHostToDevice, stream);
+        e = hipMemcpyAsync(d.J4, J4.data(), J4.size() * 4, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return bail(hip_fail(e, "upload of the run parameters"));
     rc = rewl_launch_init(d, stream);
     if (rc) return bail(fail(REWL_EDEVICE, "launch of the start-up kernel failed"));
@@ -670,10 +693,11 @@ int stitch(const rewl_ctx *h, const std::vector<double> &P, double *out)
     // normalisation
     const int64_t N = g.N;
     double ref = 0.0, target = 0.0;
-    if (h->p.model != REWL_EA && g.full_lo && std::isfinite(out[0])) {
+    const bool glass = h->p.model == REWL_EA || h->p.model == REWL_EA3;
+    if (!glass && g.full_lo && std::isfinite(out[0])) {
         ref = out[0];
         target = std::log(h->p.model == REWL_POTTS ? (double)h->p.q : 2.0);
-    } else if (h->p.model == REWL_EA && g.full_lo && g.full_hi) {
+    } else if (glass && g.full_lo && g.full_hi) {
         double mx = -INFINITY;
         for (int64_t b = 0; b < g.B; ++b) mx = std::max(mx, out[b]);
         double sum = 0.0;
@@ -705,7 +729,7 @@ int rewl_footprint(const rewl_params *p, size_t *device_bytes, size_t *lds_bytes
     int rc = validate(p, g);
     if (rc) return rc;
     if (device_bytes) *device_bytes = layout(p, g).total;
-    if (lds_bytes) *lds_bytes = sweep_lds_bytes(1, g.Wmax, g.N, p->model == REWL_EA);
+    if (lds_bytes) *lds_bytes = sweep_lds_bytes(1, g.Wmax, g.N, model_j_words(p->model));
     return REWL_OK;
 }
 
@@ -1177,18 +1201,17 @@ int server_retire(rewl_server *s)
 }
 
 // largest walkers-per-wave <= want whose LDS footprint fits all runs
-int fit_P(rewl_batch *b, int want, int extra_W, int extra_N, bool extra_ea)
+int fit_P(rewl_batch *b, int want, int extra_W, int extra_N, int extra_j_words)
 {
-    int max_W = extra_W, max_N = extra_N;
-    bool ea = extra_ea;
+    int max_W = extra_W, max_N = extra_N, jw = extra_j_words;
     for (rewl_ctx *h : b->runs) {
         if (!h) continue;
         max_W = std::max(max_W, h->g.Wmax);
         max_N = std::max(max_N, h->g.N);
-        ea = ea || h->p.model == REWL_EA;
+        jw = std::max(jw, model_j_words(h->p.model));
     }
     for (int P = want; P >= 1; P /= 2)
-        if (sweep_lds_bytes(P, max_W, max_N, ea) <= kMaxLds) return P;
+        if (sweep_lds_bytes(P, max_W, max_N, jw) <= kMaxLds) return P;
     return 0;
 }
 
@@ -1202,7 +1225,7 @@ int server_admit(rewl_server *s, int want_P)
         Geometry g;
         int rc = validate(&q.p, g);
         if (rc) return rc;
-        const int P = fit_P(b, want_P, g.Wmax, g.N, q.p.model == REWL_EA);
+        const int P = fit_P(b, want_P, g.Wmax, g.N, model_j_words(q.p.model));
         if (P == 0) break;
         rewl_ctx *h = nullptr;
         rc = make_run(&h, &q.p, nullptr, 0, b->stream);
@@ -1259,8 +1282,9 @@ int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id)
     q.p = *p;
     q.wlo = g.lo;
     q.whi = g.hi;
-    if (p->model == REWL_EA) {
-        q.couplings.assign(p->couplings, p->couplings + 2 * (size_t)g.N);
+    if (p->model == REWL_EA || p->model == REWL_EA3) {
+        q.couplings.assign(p->couplings,
+                           p->couplings + (size_t)bonds_per_site(p->model) * (size_t)g.N);
         q.p.couplings = q.couplings.data();
     } else {
         q.p.couplings = nullptr;
@@ -1270,7 +1294,7 @@ int rewl_server_submit(rewl_server *s, const rewl_params *p, int64_t *id)
     s->queue.push_back(std::move(q));
     // vector growth moved the copies; point each entry at its own again
     for (auto &e : s->queue) {
-        if (e.p.model == REWL_EA) e.p.couplings = e.couplings.data();
+        if (e.p.model == REWL_EA || e.p.model == REWL_EA3) e.p.couplings = e.couplings.data();
         e.p.window_lo = e.wlo.data();
         e.p.window_hi = e.whi.data();
     }

@@ -111,7 +111,7 @@ __device__ __forceinline__ double ln_u(uint32_t hi, uint32_t lo)
 // Neighbours of site i = r L + c on the L x L torus; the row is
 // mulhi(i, ceil(2^32 / L)), exact for i < 2^16 and L <= 256.
 struct Nbrs {
-    int rt, lf, dn, up;
+    int rt, lf, dn, up, fw, bk;  // +x, -x, +y, -y (+z, -z on the L^3 torus)
 };
 
 __device__ __forceinline__ Nbrs neighbours(int i, int L, int N, uint32_t l_magic)
@@ -123,6 +123,29 @@ __device__ __forceinline__ Nbrs neighbours(int i, int L, int N, uint32_t l_magic
     n.lf = (c == 0) ? i + L - 1 : i - 1;
     n.dn = (r + 1 == L) ? c : i + L;
     n.up = (r == 0) ? i + N - L : i - L;
+    n.fw = i;
+    n.bk = i;
+    return n;
+}
+
+// Neighbours of site i = (z L + y) L + x on the L x L x L torus, N = L^3;
+// z = mulhi(i, ceil(2^32 / L^2)) and y likewise from the remainder, exact for
+// i < 2^16.
+__device__ __forceinline__ Nbrs neighbours3(int i, int L, int N, uint32_t l_magic,
+                                            uint32_t l2_magic)
+{
+    const int L2 = L * L;
+    const int z = (int)__umulhi((uint32_t)i, l2_magic);
+    const int rem = i - z * L2;
+    const int y = (int)__umulhi((uint32_t)rem, l_magic);
+    const int x = rem - y * L;
+    Nbrs n;
+    n.rt = (x + 1 == L) ? i - x : i + 1;
+    n.lf = (x == 0) ? i + L - 1 : i - 1;
+    n.dn = (y + 1 == L) ? i - y * L : i + L;
+    n.up = (y == 0) ? i + L2 - L : i - L;
+    n.fw = (z + 1 == L) ? i - z * L2 : i + L2;
+    n.bk = (z == 0) ? i + N - L2 : i - L2;
     return n;
 }
 

@@ -12,8 +12,9 @@
 //           int64, first h int64 (round of the first merge), lo/hi h int32
 //           (bins)
 //   ex_prop, ex_acc  h uint64 (exchange proposals / acceptances of pair (k,k+1))
-//   J4      N uint32         (EA: couplings to right, left, down, up neighbour,
-//                             one int8 each, packed little-endian)
+//   J4      N uint32 (EA: couplings to right, left, down, up neighbour, one
+//           int8 each, packed little-endian) or 2N uint32 (EA3: the same, then
+//           +z, -z)
 //   round   1 int64          (rounds completed; read by the merge and exchange
 //                             kernels, advanced by advance_kernel)
 //   status  1 int32          (start-up failure flag)
@@ -29,6 +30,7 @@ struct RunDesc {
     int Npad, Wmax;
     int e_min, step;
     uint32_t l_magic;  // ceil(2^32 / L): row = mulhi(site, l_magic) for site < L*L
+    uint32_t l2_magic; // ceil(2^32 / L^2) (3D: layer = mulhi(site, l2_magic))
     uint32_t key0, key1;
     long long S;
     int schedule;      // 0 halving, 1 halving then 1/t
@@ -47,7 +49,8 @@ struct RunDesc {
     long long *first;  // per window: round of its first merge, -1 before
     int *lo, *hi;
     unsigned long long *ex_prop, *ex_acc;
-    uint32_t *J4;
+    uint32_t *J4;      // couplings per site: EA one word (+x, -x, +y, -y), EA3
+                       // two words (+x, -x, +y, -y | +z, -z), one int8 each
     long long *round;
     int *status;
 };
@@ -70,7 +73,7 @@ struct BatchDev {
     int n_runs, n_sweep, n_win, n_pair;
     int P;          // walkers per wave in the sweep (1, 2, 4, 8, 16, 32, 64)
     int max_N, max_W;
-    int any_ea;
+    int j_words;    // coupling words per site of the batch's runs (0, 1 EA, 2 EA3)
     int region;     // LDS stride of the walkers' regions: sweep_region(max_W, max_N, 64/P)
 };
 
@@ -113,12 +116,15 @@ inline size_t sweep_region(int W, int N, int G)
     return ((sweep_walker_lds(W, N, G) + 255) & ~(size_t)255) + 32;
 }
 
-// LDS bytes of one sweep work-group (P walkers, EA couplings shared by the
-// group's run: 4 N).
-inline size_t sweep_lds_bytes(int P, int W, int N, bool ea)
+// LDS bytes of one sweep work-group (P walkers, couplings shared by the
+// group's run: 4 j_words N).
+inline size_t sweep_lds_bytes(int P, int W, int N, int j_words)
 {
-    return (size_t)P * sweep_region(W, N, kWave / P) + (ea ? (size_t)N * 4 : 0);
+    return (size_t)P * sweep_region(W, N, kWave / P) + (size_t)j_words * 4 * (size_t)N;
 }
+
+// coupling words per site of a model (0 for Ising and Potts, 1 EA, 2 EA3)
+inline int model_j_words(int model) { return model == 2 ? 1 : (model == 3 ? 2 : 0); }
 
 constexpr size_t kMaxLds = 160 * 1024;
 

@@ -27,7 +27,15 @@ using namespace rewl;
 
 namespace {
 
-constexpr int kIsing = 0, kPotts = 1, kEA = 2;
+constexpr int kIsing = 0, kPotts = 1, kEA = 2, kEA3 = 3;
+
+// neighbours of a site for the model's lattice
+template <int MODEL>
+__device__ __forceinline__ Nbrs nbrs_of(int i, const RunDesc &a)
+{
+    if (MODEL == kEA3) return neighbours3(i, a.L, a.N, a.l_magic, a.l2_magic);
+    return neighbours(i, a.L, a.N, a.l_magic);
+}
 
 template <int MODEL>
 struct Step {
@@ -36,11 +44,18 @@ struct Step {
 
 // energy change of site `site` going from `old` to `nw`, spins in LDS
 template <int MODEL>
-__device__ __forceinline__ int delta_e(const int8_t *sp, const uint32_t *J4, int site, int rt,
-                                       int lf, int dn, int up, int old, int nw)
+__device__ __forceinline__ int delta_e(const int8_t *sp, const uint32_t *J4, int site,
+                                       const Nbrs &nb, int old, int nw)
 {
+    const int rt = nb.rt, lf = nb.lf, dn = nb.dn, up = nb.up;
     if (MODEL == kIsing) {
         return 2 * old * ((int)sp[rt] + (int)sp[lf] + (int)sp[dn] + (int)sp[up]);
+    } else if (MODEL == kEA3) {
+        const uint2 j = reinterpret_cast<const uint2 *>(J4)[site];
+        const int h = (int8_t)(j.x & 0xFF) * sp[rt] + (int8_t)((j.x >> 8) & 0xFF) * sp[lf] +
+                      (int8_t)((j.x >> 16) & 0xFF) * sp[dn] + (int8_t)(j.x >> 24) * sp[up] +
+                      (int8_t)(j.y & 0xFF) * sp[nb.fw] + (int8_t)((j.y >> 8) & 0xFF) * sp[nb.bk];
+        return 2 * old * h;
     } else if (MODEL == kEA) {
         const uint32_t j = J4[site];
         const int jr = (int8_t)(j & 0xFF), jl = (int8_t)((j >> 8) & 0xFF);
@@ -53,22 +68,28 @@ __device__ __forceinline__ int delta_e(const int8_t *sp, const uint32_t *J4, int
     }
 }
 
-// energy of the bonds to the right and below site i
+// energy of the bonds to the right and below site i (and behind it, 3D)
 template <int MODEL>
-__device__ __forceinline__ int bond_energy(const int8_t *sp, const uint32_t *J4, int i, int L,
-                                           int N, uint32_t l_magic)
+__device__ __forceinline__ int bond_energy(const int8_t *sp, const uint32_t *J4, int i,
+                                           const RunDesc &a)
 {
-    const Nbrs nb = neighbours(i, L, N, l_magic);
+    const Nbrs nb = nbrs_of<MODEL>(i, a);
     if (MODEL == kIsing) return -(sp[i] * sp[nb.rt] + sp[i] * sp[nb.dn]);
+    if (MODEL == kEA3) {
+        const uint2 j = reinterpret_cast<const uint2 *>(J4)[i];
+        return -((int8_t)(j.x & 0xFF) * sp[i] * sp[nb.rt] +
+                 (int8_t)((j.x >> 16) & 0xFF) * sp[i] * sp[nb.dn] +
+                 (int8_t)(j.y & 0xFF) * sp[i] * sp[nb.fw]);
+    }
     if (MODEL == kPotts) return -((sp[i] == sp[nb.rt]) + (sp[i] == sp[nb.dn]));
     const uint32_t j = J4[i];
     const int jr = (int8_t)(j & 0xFF), jd = (int8_t)((j >> 16) & 0xFF);
     return -(jr * sp[i] * sp[nb.rt] + jd * sp[i] * sp[nb.dn]);
 }
 
-// a start-up move: site, Potts offset and the four neighbours
+// a start-up move: site, Potts offset and the neighbours (16 bits each)
 struct Move {
-    uint32_t site_r1, nb_rl, nb_du, pad;
+    uint32_t site_r1, nb_rl, nb_du, nb_fb;
 };
 
 __device__ __forceinline__ int dist_to(int E, int elo, int ehi)
@@ -99,22 +120,23 @@ __device__ int block_sum_256(int v, int *scratch)
 template <int MODEL>
 __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
 {
-    const int w = blockIdx.x, k = w / a.m, N = a.N, L = a.L;
+    const int w = blockIdx.x, k = w / a.m, N = a.N;
     extern __shared__ __align__(16) unsigned char smem[];
     Move *stage = reinterpret_cast<Move *>(smem);
     int *scratch = reinterpret_cast<int *>(stage + kWave);   // 8 ints
+    constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);  // coupling words per site
     uint32_t *J_s = reinterpret_cast<uint32_t *>(scratch + 8);
-    int8_t *sp = reinterpret_cast<int8_t *>(J_s + (MODEL == kEA ? N : 0));
+    int8_t *sp = reinterpret_cast<int8_t *>(J_s + JW * N);
     __shared__ int sh_E, sh_stop, sh_used;
 
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const U4 r = philox((uint32_t)i, 0u, (uint32_t)w, 1u, a.key0, a.key1);
         sp[i] = (MODEL == kPotts) ? (int8_t)mulhi32(r.x, (uint32_t)a.q) : ((r.x >> 31) ? 1 : -1);
-        if (MODEL == kEA) J_s[i] = a.J4[i];
     }
+    for (int i = threadIdx.x; i < JW * N; i += blockDim.x) J_s[i] = a.J4[i];
     __syncthreads();
     int e = 0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) e += bond_energy<MODEL>(sp, J_s, i, L, N, a.l_magic);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) e += bond_energy<MODEL>(sp, J_s, i, a);
     e = block_sum_256(e, scratch);
     const int elo = a.e_min + a.lo[k] * a.step, ehi = a.e_min + a.hi[k] * a.step;
     if (threadIdx.x == 0) {
@@ -130,11 +152,12 @@ __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
             const U4 r = philox((uint32_t)c, (uint32_t)(c >> 32), (uint32_t)w, 2u, a.key0, a.key1);
             const int site = (int)mulhi32(r.x, (uint32_t)N);
             const uint32_t r1 = (MODEL == kPotts) ? 1u + mulhi32(r.y, (uint32_t)(a.q - 1)) : 0u;
-            const Nbrs nb = neighbours(site, L, N, a.l_magic);
+            const Nbrs nb = nbrs_of<MODEL>(site, a);
             Move p;
             p.site_r1 = (uint32_t)site | (r1 << 16);
             p.nb_rl = (uint32_t)nb.rt | ((uint32_t)nb.lf << 16);
             p.nb_du = (uint32_t)nb.dn | ((uint32_t)nb.up << 16);
+            p.nb_fb = (uint32_t)nb.fw | ((uint32_t)nb.bk << 16);
             stage[threadIdx.x] = p;
         }
         __syncthreads();
@@ -144,7 +167,7 @@ __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
                 if (dist_to(E, elo, ehi) == 0) { stop = 1; break; }
                 const unsigned long long dd = d + j;
                 if (dd == cap) {
-                    if (MODEL == kEA) { a.status[0] = 1; stop = 1; break; }
+                    if (MODEL == kEA || MODEL == kEA3) { a.status[0] = 1; stop = 1; break; }
                     const int8_t v = (MODEL == kPotts) ? 0 : 1;
                     for (int i = 0; i < N; ++i) sp[i] = v;
                     E = -2 * N;
@@ -160,9 +183,10 @@ __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
                 } else {
                     nw = -old;
                 }
-                const int En = E + delta_e<MODEL>(sp, J_s, site, (int)(p.nb_rl & 0xFFFFu),
-                                                  (int)(p.nb_rl >> 16), (int)(p.nb_du & 0xFFFFu),
-                                                  (int)(p.nb_du >> 16), old, nw);
+                const Nbrs nb{(int)(p.nb_rl & 0xFFFFu), (int)(p.nb_rl >> 16),
+                              (int)(p.nb_du & 0xFFFFu), (int)(p.nb_du >> 16),
+                              (int)(p.nb_fb & 0xFFFFu), (int)(p.nb_fb >> 16)};
+                const int En = E + delta_e<MODEL>(sp, J_s, site, nb, old, nw);
                 if (dist_to(En, elo, ehi) <= dist_to(E, elo, ehi)) {
                     sp[site] = (int8_t)nw;
                     E = En;
@@ -251,7 +275,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     constexpr int STEP = Step<MODEL>::value;
     constexpr int ADDR_PER_E = 8 / STEP;   // bytes of ln g per energy unit
     const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-    const int N = a.N, L = a.L, q = a.q;
+    const int N = a.N, q = a.q;
     const int w = it.w0 + grp;
     const int k = w / a.m;
     // a walker group is live when it exists and its window is still running
@@ -291,8 +315,8 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         for (int i = gl; i < N; i += G) tag[i] = (TagT)0;
     }
     for (int i = gl; i < 2; i += G) stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
-    if (MODEL == kEA)
-        for (int i = lane; i < N; i += kWave) J_s[i] = a.J4[i];
+    constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);  // coupling words per site
+    for (int i = lane; i < JW * N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
 
     const int elo = a.e_min + lo * STEP;
@@ -313,7 +337,8 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     // state-independent part of an attempt: Philox draw, site, neighbours,
     // Potts offset, ln u
     struct Draw {
-        int site, rt, lf, dn, up;
+        int site;
+        Nbrs nb;
         uint32_t r1;
         double thr;
     };
@@ -341,11 +366,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         } else if (piece == 5) {
             st.out.site = (int)mulhi32(st.c.x, (uint32_t)N);
             st.out.r1 = (MODEL == kPotts) ? 1u + mulhi32(st.c.y, (uint32_t)(q - 1)) : 0u;
-            const Nbrs nb = neighbours(st.out.site, L, N, a.l_magic);
-            st.out.rt = nb.rt;
-            st.out.lf = nb.lf;
-            st.out.dn = nb.dn;
-            st.out.up = nb.up;
+            st.out.nb = nbrs_of<MODEL>(st.out.site, a);
         } else if (piece == 6) {
             st.lu = ln_u_reduce(st.c.z, st.c.w);
         } else {
@@ -367,10 +388,11 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         if (active) {
             const int old = sp[cur.site];
             const int nw = new_state<MODEL>(old, cur.r1, q);
-            const int dE = delta_e<MODEL>(sp, J_s, cur.site, cur.rt, cur.lf, cur.dn, cur.up, old, nw);
+            const int dE = delta_e<MODEL>(sp, J_s, cur.site, cur.nb, old, nw);
             tag_set<G>(tag, cur.site, bit);
-            const uint64_t seen = (uint64_t)tag[cur.site] | tag[cur.rt] | tag[cur.lf] | tag[cur.dn] |
-                                  tag[cur.up];
+            uint64_t seen = (uint64_t)tag[cur.site] | tag[cur.nb.rt] | tag[cur.nb.lf] |
+                            tag[cur.nb.dn] | tag[cur.nb.up];
+            if (MODEL == kEA3) seen |= (uint64_t)tag[cur.nb.fw] | tag[cur.nb.bk];
             Prop p;
             p.thr = cur.thr;
             p.lnf = one_over_t ? Wd / (double)(t0 + (unsigned long long)base + gl + 1) : lnf;
@@ -440,11 +462,10 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                     // some group's attempt j is flagged: every group recomputes
                     // from its current spins, the flagged ones keep the result
                     const int s = (int)(r0.sp_off - sp_base);
-                    const Nbrs nb = neighbours(s, L, N, a.l_magic);
+                    const Nbrs nb = nbrs_of<MODEL>(s, a);
                     const int o2 = sp[s];
                     const int n2 = new_state<MODEL>(o2, (r0.flags >> 16) & 0x7Fu, q);
-                    const int d2 = delta_e<MODEL>(sp, J_s, s, nb.rt, nb.lf, nb.dn, nb.up, o2, n2) *
-                                   ADDR_PER_E;
+                    const int d2 = delta_e<MODEL>(sp, J_s, s, nb, o2, n2) * ADDR_PER_E;
                     const double g2 = ld(baddr + (uint32_t)d2);
                     const bool f = (r0.flags & 0x80000000u) != 0;
                     old = f ? o2 : old;
@@ -519,7 +540,8 @@ __global__ __launch_bounds__(kWave) void sweep_kernel(BatchDev bd)
     switch (a.model) {
     case kIsing: sweep_body<kIsing, P>(a, it, bd, smem); break;
     case kPotts: sweep_body<kPotts, P>(a, it, bd, smem); break;
-    default: sweep_body<kEA, P>(a, it, bd, smem); break;
+    case kEA: sweep_body<kEA, P>(a, it, bd, smem); break;
+    default: sweep_body<kEA3, P>(a, it, bd, smem); break;
     }
 }
 
@@ -738,7 +760,7 @@ template <int MODEL>
 int launch_init_t(const RunDesc &a, hipStream_t s)
 {
     const size_t lds = kWave * sizeof(Move) + 8 * sizeof(int) +
-                       (MODEL == kEA ? (size_t)a.N * 4 : 0) + (size_t)a.N + 16;
+                       (size_t)model_j_words(MODEL) * 4 * (size_t)a.N + (size_t)a.N + 16;
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -770,7 +792,8 @@ int rewl_launch_init(const RunDesc &a, void *stream)
     switch (a.model) {
     case kIsing: return launch_init_t<kIsing>(a, s);
     case kPotts: return launch_init_t<kPotts>(a, s);
-    default: return launch_init_t<kEA>(a, s);
+    case kEA: return launch_init_t<kEA>(a, s);
+    default: return launch_init_t<kEA3>(a, s);
     }
 }
 
@@ -778,7 +801,7 @@ int rewl_launch_round(const BatchDev &b, void *stream, void *ev0, void *ev1)
 {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0 = reinterpret_cast<hipEvent_t>(ev0), e1 = reinterpret_cast<hipEvent_t>(ev1);
-    const size_t lds = sweep_lds_bytes(b.P, b.max_W, b.max_N, b.any_ea != 0);
+    const size_t lds = sweep_lds_bytes(b.P, b.max_W, b.max_N, b.j_words);
     if (lds > kMaxLds) return -1;
     if (e0 && hipEventRecord(e0, s) != hipSuccess) return -3;
     if (b.n_sweep > 0) {

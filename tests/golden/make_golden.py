@@ -1,9 +1,11 @@
-"""Write the exact 2D Ising densities of states used by the tests.
+"""Write the exact densities of states used by the tests.
 
-Calls only oracle.exact (Kaufman's finite-torus partition function, inverted as
-Beale did).  Output per L: one line per energy level, "E g(E)" for L <= 16
-(exact integers) and "E ln g(E)" with 17 significant digits for larger L.
-Usage: python tests/golden/make_golden.py [L ...]   (default: 8 16 32)
+Calls only oracle.exact.  2D Ising: Kaufman's finite-torus partition function,
+inverted as Beale did; one line per energy level, "E g(E)" for L <= 16 (exact
+integers) and "E ln g(E)" with 17 significant digits for larger L.  3D +-J
+glass, 3x3x3, couplings workloads.ea3_couplings(3, 1): enumeration of all 2^27
+configurations (a few minutes), "E g(E)".
+Usage: python tests/golden/make_golden.py [L ... | ea3]   (default: 8 16 32)
 """
 import math
 import os
@@ -13,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import exact  # noqa: E402
+from workloads import ea3_couplings  # noqa: E402
 
 
 def write(L):
@@ -35,6 +38,23 @@ def write(L):
     print("wrote", path)
 
 
+def write_ea3(L=3, seed=1):
+    g = exact.brute_dos("ea3", L, couplings=ea3_couplings(L, seed))
+    assert sum(g.values()) == 2 ** (L ** 3)
+    path = os.path.join(HERE, f"ea3_L{L}_seed{seed}.txt")
+    with open(path, "w") as f:
+        f.write(f"# exact DOS of the 3D +-J glass {L}x{L}x{L}, couplings "
+                f"workloads.ea3_couplings({L}, {seed}), E = -sum J s_i s_j; written by "
+                f"tests/golden/make_golden.py from oracle.exact\n# columns: E g(E)\n")
+        for e in sorted(g):
+            f.write(f"{e} {g[e]}\n")
+    print("wrote", path)
+
+
 if __name__ == "__main__":
-    for L in [int(a) for a in sys.argv[1:]] or [8, 16, 32]:
-        write(L)
+    args = sys.argv[1:]
+    if args == ["ea3"]:
+        write_ea3()
+    else:
+        for L in [int(a) for a in args] or [8, 16, 32]:
+            write(L)

@@ -10,7 +10,16 @@ converged run must agree too.
 import numpy as np
 import pytest
 
-from workloads import ea_couplings, run_params
+from workloads import ea3_couplings, ea_couplings, run_params
+
+
+def _with_couplings(kw):
+    kw = dict(kw)
+    if kw["model"] == "ea":
+        kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+    elif kw["model"] == "ea3":
+        kw["couplings"] = ea3_couplings(kw["L"], kw["seed"])
+    return kw
 
 pytestmark = pytest.mark.gpu
 
@@ -93,14 +102,16 @@ CASES = [
                          lnf_final=0.3, seed=7)),
     ("ising12_range", dict(model="ising", L=12, n_windows=3, walkers_per_window=2, S=500,
                            e_min=-240, e_max=40, lnf_final=1e-2, seed=8)),
+    ("ea3_4", dict(model="ea3", L=4, n_windows=3, walkers_per_window=2, S=700, lnf_final=1e-2,
+                   seed=13)),
+    ("ea3_3_odd", dict(model="ea3", L=3, n_windows=2, walkers_per_window=3, S=130,
+                       lnf_final=1e-2, seed=14)),
 ]
 
 
 @pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
 def test_rounds_bitexact(gpu, orc, name, kw):
-    kw = dict(kw)
-    if kw["model"] == "ea":
-        kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+    kw = _with_couplings(kw)
     g, o = _pair(gpu, orc, **kw)
     assert_same_state(g, o, "start-up")
     done_rounds = 0
@@ -126,9 +137,7 @@ ONE_OVER_T = [
 
 @pytest.mark.parametrize("name,kw,steps", ONE_OVER_T, ids=[c[0] for c in ONE_OVER_T])
 def test_one_over_t_rounds_bitexact(gpu, orc, name, kw, steps):
-    kw = dict(kw, schedule="1/t")
-    if kw["model"] == "ea":
-        kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
+    kw = _with_couplings(dict(kw, schedule="1/t"))
     g, o = _pair(gpu, orc, **kw)
     done_rounds = 0
     for rounds in steps:
@@ -197,11 +206,12 @@ def test_ising8_full_run_bitexact(gpu, orc):
     assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
 
 
-@pytest.mark.parametrize("name,rounds", [("ising32", 3), ("potts64", 1), ("ea24", 2)])
+@pytest.mark.parametrize("name,rounds", [("ising32", 3), ("potts64", 1), ("ea24", 2),
+                                         ("ea3d12", 2)])
 def test_full_size_rounds_bitexact(gpu, orc, name, rounds):
     """The full-size workloads (32x32 Ising 16x4, 64x64 q=10 Potts 32x8, 24x24
-    +-J 8x4) for a few rounds of 10^4 attempts per walker, in the launch
-    configuration the benchmark times."""
+    +-J 8x4, 12x12x12 +-J 8x4) for a few rounds of 10^4 attempts per walker,
+    in the launch configuration the benchmark times."""
     p = run_params(name, seed=1)
     kw = _kw(p)
     print("case:", name, flush=True)
@@ -232,17 +242,12 @@ MIXED = [
          seed=22),
     dict(model="ea", L=8, n_windows=5, walkers_per_window=2, S=1000, lnf_final=1e-2, seed=23),
     dict(model="ising", L=6, n_windows=2, walkers_per_window=1, S=333, lnf_final=1e-2, seed=24),
+    dict(model="ea3", L=4, n_windows=3, walkers_per_window=2, S=500, lnf_final=1e-2, seed=25),
 ]
 
 
 def _mixed():
-    out = []
-    for kw in MIXED:
-        kw = dict(kw)
-        if kw["model"] == "ea":
-            kw["couplings"] = ea_couplings(kw["L"], kw["seed"])
-        out.append(kw)
-    return out
+    return [_with_couplings(kw) for kw in MIXED]
 
 
 @pytest.mark.parametrize("P", [1, 2, 4, 8])

@@ -148,13 +148,14 @@ def test_energy_matches_brute_force_definition(oracle_lib):
             assert oracle_lib.energy("potts", L, p, q=5) == -((p == p[rt]).sum() + (p == p[dn]).sum())
 
 
-@pytest.mark.parametrize("model,q", [("ising", 2), ("potts", 4), ("ea", 2)])
-def test_walker_energy_tracks_spins(oracle_lib, model, q):
+@pytest.mark.parametrize("model,q,L", [("ising", 2, 6), ("potts", 4, 6), ("ea", 2, 6),
+                                       ("ea3", 2, 4), ("ea3", 2, 3)])
+def test_walker_energy_tracks_spins(oracle_lib, model, q, L):
     """After rounds of sweeps and exchanges every walker's E equals E(spins)."""
-    from workloads import ea_couplings
+    from workloads import ea3_couplings, ea_couplings
 
-    L = 6
-    J = ea_couplings(L, 3) if model == "ea" else None
+    J = {"ea": lambda: ea_couplings(L, 3), "ea3": lambda: ea3_couplings(L, 3)}.get(
+        model, lambda: None)()
     run = oracle_lib.Run(model, L, q=q, couplings=J, n_windows=3, walkers_per_window=2,
                          S=500, seed=9)
     for _ in range(5):
@@ -587,7 +588,65 @@ def test_descent_reaches_every_window(oracle_lib):
         assert win["lo"] <= b <= win["hi"]
 
 
+def test_ea3_energy_definition(oracle_lib):
+    """3D glass energy -sum over the 3N bonds (site, +x / +y / +z neighbour) of
+    J s s, against a numpy evaluation of that definition, and the reference
+    states: all spins up gives -sum J."""
+    from workloads import ea3_couplings
+
+    rng = np.random.default_rng(4)
+    for L in (2, 3, 5):
+        N = L ** 3
+        J = ea3_couplings(L, L)
+        idx = np.arange(N).reshape(L, L, L)
+        nbr = [np.roll(idx, -1, axis=ax).ravel() for ax in (2, 1, 0)]
+        Jr = J.reshape(N, 3).astype(np.int64)
+        for _ in range(20):
+            s = rng.choice(np.array([-1, 1], dtype=np.int8), size=N)
+            ref = -sum((Jr[:, a] * s * s[nbr[a]]).sum() for a in range(3))
+            assert oracle_lib.energy("ea3", L, s, J) == ref
+        assert oracle_lib.energy("ea3", L, np.ones(N, np.int8), J) == -int(J.astype(int).sum())
+
+
+def test_ea3_brute_force_pins():
+    """The 2x2x2 glass enumerated: sum g = 2^N, g(E) = g(-E) (the cubic torus of
+    even L is bipartite: flipping one sublattice maps E to -E), energies on the
+    class -3N + 2 n_neg (mod 4)."""
+    from oracle import exact
+    from workloads import ea3_couplings
+
+    for seed in (1, 2, 3):
+        J = ea3_couplings(2, seed)
+        g = exact.brute_dos("ea3", 2, couplings=J)
+        assert sum(g.values()) == 2 ** 8
+        assert all(g[e] == g.get(-e, 0) for e in g)
+        n_neg = int((J < 0).sum())
+        assert all((e - (-24 + 2 * n_neg)) % 4 == 0 for e in g)
+
+
+def test_ea3_converges_to_brute_force(oracle_lib):
+    """REWL on 2x2x2 glasses against exact enumeration."""
+    from oracle import exact
+    from workloads import ea3_couplings
+
+    for seed in (1, 2):
+        J = ea3_couplings(2, seed)
+        g = exact.brute_dos("ea3", 2, couplings=J)
+        run = oracle_lib.Run("ea3", 2, couplings=J, n_windows=2, walkers_per_window=2,
+                             S=3000, lnf_final=1e-6, seed=seed)
+        assert run.run()
+        E = run.energies()
+        ref = np.array([math.log(g[e]) if g.get(e, 0) else -np.inf for e in E])
+        assert _max_err(run.lng(), ref) < 0.05
+
+
 def test_invalid_arguments(oracle_lib):
+    from workloads import ea3_couplings
+
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ea3", 33, couplings=ea3_couplings(33, 1))
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.Run("ea3", 4)                       # no couplings
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.Run("ising", 2)
     with pytest.raises(oracle_lib.OracleError):

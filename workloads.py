@@ -12,7 +12,8 @@ from __future__ import annotations
 import numpy as np
 
 # Workload parameters.  Energies: Ising and +-J span [-2N, 2N] in steps of 4,
-# Potts [-2N, 0] in steps of 1 (N = L*L).
+# Potts [-2N, 0] in steps of 1 (N = L*L); the 3D +-J glass [-3N, 3N] in steps
+# of 4 (N = L^3).
 CONFIGS = {
     # 2D Ising 8x8, 4 windows x 2 walkers, ln f 1 -> 1e-6 (the small parity case)
     "ising8": dict(model="ising", L=8, q=2, n_windows=4, overlap=0.75, walkers_per_window=2,
@@ -26,6 +27,10 @@ CONFIGS = {
     # one 2D +-J Edwards-Anderson glass 24x24, 8 windows x 4 walkers (256 of them batched)
     "ea24": dict(model="ea", L=24, q=2, n_windows=8, overlap=0.75, walkers_per_window=4,
                  flatness=0.8, lnf_init=1.0, lnf_final=1e-6, S=10_000),
+    # one 3D +-J glass 12x12x12 (the paper's ground-state test size), 8 windows
+    # x 4 walkers, ln f final 1e-6
+    "ea3d12": dict(model="ea3", L=12, q=2, n_windows=8, overlap=0.75, walkers_per_window=4,
+                   flatness=0.8, lnf_init=1.0, lnf_final=1e-6, S=10_000),
 }
 
 
@@ -35,7 +40,16 @@ def ea_couplings(L, seed):
     return np.where(rng.random(2 * L * L) < 0.5, 1, -1).astype(np.int8)
 
 
+def ea3_couplings(L, seed):
+    """+-1 couplings with p = 1/2 on the L^3 torus, laid out [3i + a] = J(i,
+    next site along axis a = x, y, z), sites i = (z L + y) L + x."""
+    rng = np.random.default_rng(np.random.SeedSequence([0xEA3, int(seed)]))
+    return np.where(rng.random(3 * L ** 3) < 0.5, 1, -1).astype(np.int8)
+
+
 def full_range(model, L):
+    if model == "ea3":
+        return (-3 * L ** 3, 3 * L ** 3)
     N = L * L
     return (-2 * N, 0) if model == "potts" else (-2 * N, 2 * N)
 
@@ -50,7 +64,9 @@ def run_params(name, seed=1, **over):
     p["seed"] = int(seed)
     if p["model"] == "ea" and "couplings" not in p:
         p["couplings"] = ea_couplings(p["L"], seed)
-    elif p["model"] != "ea":
+    elif p["model"] == "ea3" and "couplings" not in p:
+        p["couplings"] = ea3_couplings(p["L"], seed)
+    elif p["model"] not in ("ea", "ea3"):
         p["couplings"] = None
     return p
 
