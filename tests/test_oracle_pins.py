@@ -640,6 +640,36 @@ def test_ea3_converges_to_brute_force(oracle_lib):
         assert _max_err(run.lng(), ref) < 0.05
 
 
+def _load_ea3_golden():
+    path = os.path.join(ROOT, "tests", "golden", "ea3_L3_seed1.txt")
+    g = {}
+    with open(path) as f:
+        for line in f:
+            if not line.startswith("#"):
+                e, n = line.split()
+                g[int(e)] = int(n)
+    return g
+
+
+def test_ea3_golden_3x3x3(oracle_lib):
+    """The stored 3x3x3 glass DOS (all 2^27 configurations enumerated): sum rule,
+    energy class, and REWL in the oracle converging to it (4 windows x 4
+    walkers, ln f to 1e-6; seeds 2-4 give 0.06-0.08)."""
+    from workloads import ea3_couplings
+
+    g = _load_ea3_golden()
+    J = ea3_couplings(3, 1)
+    assert sum(g.values()) == 2 ** 27
+    n_neg = int((J < 0).sum())
+    assert all((e - (-81 + 2 * n_neg)) % 4 == 0 for e in g)
+    run = oracle_lib.Run("ea3", 3, couplings=J, n_windows=4, walkers_per_window=4, S=5000,
+                         lnf_final=1e-6, seed=2)
+    assert run.run()
+    E = run.energies()
+    ref = np.array([math.log(g[e]) if g.get(e, 0) else -np.inf for e in E])
+    assert _max_err(run.lng(), ref) < 0.15
+
+
 def test_invalid_arguments(oracle_lib):
     from workloads import ea3_couplings
 
