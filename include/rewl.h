@@ -213,6 +213,19 @@ int rewl_partition_balanced(int64_t n_bins, int n_windows, double overlap, int p
  * run left unvisited (-inf) gets mean -inf and err NaN.  runs >= 2. */
 int rewl_jackknife(const double *lng, int runs, int64_t n_bins, double *mean, double *err);
 
+/* Checkpoint and resume.  rewl_save waits for the run's pending work, then
+ * writes its parameters, couplings, windows and complete device state to
+ * `path` (through path.tmp, renamed when complete; the caller owns the path).
+ * rewl_load recreates the run from such a file -- device memory as in
+ * rewl_create_ex -- so that stepping it continues exactly as the saved run
+ * would have (same rounds, same results, bit for bit).  REWL_ECORRUPT: not a
+ * checkpoint, truncated, or checksum (FNV-1a 64 over the file) mismatch;
+ * REWL_EINVAL: the file cannot be opened or written.  Works for a run of a
+ * batch too (it is saved alone and loads as a run of its own). */
+int rewl_save(rewl_ctx *h, const char *path);
+int rewl_load(rewl_ctx **out, const char *path, void *device_buffer, size_t buffer_bytes,
+              void *hip_stream);
+
 int rewl_set_timing(rewl_ctx *h, int on);
 int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches);
 

@@ -73,6 +73,8 @@ def lib():
         L.rewl_set_timing.argtypes = [P, i32]
         L.rewl_get_first_merge.argtypes = [P, P, i32]
         L.rewl_jackknife.argtypes = [P, i32, i64, P, P]
+        L.rewl_save.argtypes = [P, C.c_char_p]
+        L.rewl_load.argtypes = [C.POINTER(P), C.c_char_p, P, C.c_size_t, P]
         L.rewl_partition_balanced.argtypes = [i64, i32, dbl, i32, P, P, P, P, P]
         L.rewl_get_timing.argtypes = [P, C.POINTER(dbl), C.POINTER(i64)]
         L.rewl_batch_create.argtypes = [C.POINTER(P), P, i32, i32, P]
@@ -318,6 +320,32 @@ class Run(RunView):
         ms, n = C.c_double(), C.c_int64()
         _check(lib().rewl_get_timing(self._h, C.byref(ms), C.byref(n)), "rewl_get_timing")
         return ms.value, n.value
+
+    def save(self, path):
+        """Checkpoint the run (rewl_save)."""
+        _check(lib().rewl_save(self._h, os.fsencode(path)), "rewl_save")
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """Resume a run from a checkpoint (rewl_load) into a torch-owned buffer."""
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        self = cls.__new__(cls)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        # the state's size is known only from the file: the library allocates
+        self._buf = None
+        h = C.c_void_p()
+        _check(lib().rewl_load(C.byref(h), os.fsencode(path), None, 0,
+                               C.c_void_p(self._stream.cuda_stream)), "rewl_load")
+        # model and L follow the 8-byte tag of the file (int32 each)
+        with open(path, "rb") as f:
+            head = f.read(16)
+        model, L = np.frombuffer(head[8:16], dtype="<i4")
+        names = {v: k for k, v in MODELS.items()}
+        self._attach(h, names[int(model)], int(L), dict(checkpoint=str(path)))
+        return self
 
 
 class Batch:

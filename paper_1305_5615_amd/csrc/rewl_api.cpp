@@ -504,7 +504,7 @@ void free_batch(rewl_batch *b)
 // Make one run: validate, lay out, allocate (or adopt) its slab, upload its
 // parameters and run the start-up kernel on `stream`.
 int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t buffer_bytes,
-             hipStream_t stream)
+             hipStream_t stream, const void *slab = nullptr, size_t slab_bytes = 0)
 {
     *out = nullptr;
     Geometry g;
@@ -579,6 +579,15 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     d.round = (long long *)(b + h->l.round);
     d.status = (int *)(b + h->l.status);
 
+    if (slab) {
+        // resume: the saved device state replaces the start-up
+        if (slab_bytes != h->l.total) return bail(fail(REWL_ECORRUPT, "saved state has the wrong size"));
+        hipError_t e = hipMemcpyAsync(h->base, slab, slab_bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "upload of the saved state"));
+        *out = h;
+        return REWL_OK;
+    }
     const int H = p->n_windows, N = g.N, L = p->L;
     std::vector<double> lnf(H, p->lnf_init);
     std::vector<long long> fin(H, -1);
@@ -752,6 +761,161 @@ int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer, si
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     rewl_ctx *h = nullptr;
     int rc = make_run(&h, p, device_buffer, buffer_bytes, stream);
+    if (rc) return rc;
+    rewl_batch *b = new_batch(stream, 1);
+    if (!b) {
+        free_run(h);
+        return fail(REWL_ENOMEM, "host allocation failed");
+    }
+    b->runs.push_back(h);
+    b->owns_runs = true;
+    h->batch = b;
+    h->own_batch = true;
+    *out = h;
+    return REWL_OK;
+}
+
+extern "C++" {
+namespace {
+
+// checkpoint file: "REWLSAV1", the parameters field by field, the couplings,
+// the windows, the device slab, then an FNV-1a 64 checksum of everything before
+uint64_t fnv1a(const char *p, size_t n)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= (uint8_t)p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+template <class T> void put(std::string &s, const T &v) { s.append((const char *)&v, sizeof(T)); }
+
+struct Reader {
+    const std::string &s;
+    size_t at = 0;
+    bool ok = true;
+    template <class T> T get()
+    {
+        T v{};
+        if (at + sizeof(T) > s.size()) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, s.data() + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    const char *bytes(size_t n)
+    {
+        if (at + n > s.size()) {
+            ok = false;
+            return nullptr;
+        }
+        const char *p = s.data() + at;
+        at += n;
+        return p;
+    }
+};
+
+const char kMagic[8] = {'R', 'E', 'W', 'L', 'S', 'A', 'V', '1'};
+
+}  // namespace
+}  // extern "C++"
+
+int rewl_save(rewl_ctx *h, const char *path)
+{
+    if (!h || !path) return fail(REWL_EINVAL, "bad handle or path");
+    hipStream_t stream = h->batch ? h->batch->stream : nullptr;
+    std::vector<char> slab(h->l.total);
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(slab.data(), h->base, slab.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "download of the run state");
+    const rewl_params &p = h->p;
+    std::string s(kMagic, 8);
+    put<int32_t>(s, p.model);
+    put<int32_t>(s, p.L);
+    put<int32_t>(s, p.q);
+    put<int32_t>(s, p.n_windows);
+    put<int32_t>(s, p.walkers_per_window);
+    put<int32_t>(s, p.schedule);
+    put<int64_t>(s, p.e_min);
+    put<int64_t>(s, p.e_max);
+    put<double>(s, p.overlap);
+    put<double>(s, p.flatness);
+    put<double>(s, p.lnf_init);
+    put<double>(s, p.lnf_final);
+    put<int64_t>(s, p.attempts_per_round);
+    put<uint64_t>(s, p.seed);
+    put<uint64_t>(s, (uint64_t)h->couplings.size());
+    s.append((const char *)h->couplings.data(), h->couplings.size());
+    for (int k = 0; k < p.n_windows; ++k) put<int64_t>(s, h->g.lo[k]);
+    for (int k = 0; k < p.n_windows; ++k) put<int64_t>(s, h->g.hi[k]);
+    put<uint64_t>(s, (uint64_t)slab.size());
+    s.append(slab.data(), slab.size());
+    put<uint64_t>(s, fnv1a(s.data(), s.size()));
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(REWL_EINVAL, "cannot open the checkpoint file for writing");
+    const bool wrote = std::fwrite(s.data(), 1, s.size(), f) == s.size();
+    const bool closed = std::fclose(f) == 0;
+    if (!wrote || !closed || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(REWL_EINVAL, "writing the checkpoint file failed");
+    }
+    return REWL_OK;
+}
+
+int rewl_load(rewl_ctx **out, const char *path, void *device_buffer, size_t buffer_bytes,
+              void *hip_stream)
+{
+    if (!out || !path) return fail(REWL_EINVAL, "out or path is NULL");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(REWL_EINVAL, "cannot open the checkpoint file");
+    std::string s;
+    char buf[1 << 16];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+    std::fclose(f);
+    if (s.size() < 16 || std::memcmp(s.data(), kMagic, 8) != 0)
+        return fail(REWL_ECORRUPT, "not a checkpoint file");
+    uint64_t sum;
+    std::memcpy(&sum, s.data() + s.size() - 8, 8);
+    if (fnv1a(s.data(), s.size() - 8) != sum) return fail(REWL_ECORRUPT, "checkpoint checksum mismatch");
+    Reader r{s, 8};
+    rewl_params p{};
+    p.model = r.get<int32_t>();
+    p.L = r.get<int32_t>();
+    p.q = r.get<int32_t>();
+    p.n_windows = r.get<int32_t>();
+    p.walkers_per_window = r.get<int32_t>();
+    p.schedule = r.get<int32_t>();
+    p.e_min = r.get<int64_t>();
+    p.e_max = r.get<int64_t>();
+    p.overlap = r.get<double>();
+    p.flatness = r.get<double>();
+    p.lnf_init = r.get<double>();
+    p.lnf_final = r.get<double>();
+    p.attempts_per_round = r.get<int64_t>();
+    p.seed = r.get<uint64_t>();
+    const uint64_t nc = r.get<uint64_t>();
+    const char *cp = r.bytes((size_t)nc);
+    if (!r.ok || p.n_windows < 1 || p.n_windows > (1 << 20)) return fail(REWL_ECORRUPT, "truncated checkpoint");
+    std::vector<int8_t> couplings(cp, cp + nc);
+    std::vector<int64_t> lo((size_t)p.n_windows), hi((size_t)p.n_windows);
+    for (auto &v : lo) v = r.get<int64_t>();
+    for (auto &v : hi) v = r.get<int64_t>();
+    const uint64_t ns = r.get<uint64_t>();
+    const char *slab = r.bytes((size_t)ns);
+    if (!r.ok || r.at + 8 != s.size()) return fail(REWL_ECORRUPT, "truncated checkpoint");
+    p.couplings = couplings.empty() ? nullptr : couplings.data();
+    p.window_lo = lo.data();
+    p.window_hi = hi.data();
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    rewl_ctx *h = nullptr;
+    int rc = make_run(&h, &p, device_buffer, buffer_bytes, stream, slab, (size_t)ns);
     if (rc) return rc;
     rewl_batch *b = new_batch(stream, 1);
     if (!b) {

@@ -104,3 +104,20 @@ def test_jackknife_matches_oracle():
     assert np.array_equal(fin, np.isfinite(m2)) and np.isnan(e2[5])
     assert np.allclose(m1[fin], m2[fin], rtol=1e-14, atol=0)
     assert np.allclose(e1[fin], e2[fin], rtol=1e-9, atol=1e-13)
+
+
+def test_load_rejects_non_checkpoints(tmp_path):
+    """rewl_load refuses a file that is not a checkpoint before touching the
+    GPU (REWL_ECORRUPT), and a missing file with REWL_EINVAL."""
+    import ctypes as C
+
+    import paper_1305_5615_amd as rewl
+
+    junk = tmp_path / "junk.rewl"
+    junk.write_bytes(b"not a checkpoint at all" * 10)
+    h = C.c_void_p()
+    assert rewl.lib().rewl_load(C.byref(h), str(junk).encode(), None, 0, None) == -5
+    assert rewl.lib().rewl_load(C.byref(h), str(tmp_path / "none").encode(), None, 0, None) == -1
+    # a valid tag with a wrong checksum
+    junk.write_bytes(b"REWLSAV1" + bytes(64))
+    assert rewl.lib().rewl_load(C.byref(h), str(junk).encode(), None, 0, None) == -5

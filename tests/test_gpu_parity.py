@@ -191,6 +191,45 @@ def test_balanced_partition_run_bitexact(gpu, orc, model, L, q):
     assert np.array_equal(lg[fin].view(np.uint64), lo_[fin].view(np.uint64))
 
 
+@pytest.mark.parametrize("kw", [
+    dict(model="ising", L=8, n_windows=4, walkers_per_window=2, S=1000, lnf_final=1e-3, seed=31),
+    dict(model="ea3", L=4, n_windows=3, walkers_per_window=2, S=700, lnf_final=1e-3, seed=32),
+    dict(model="potts", L=6, q=3, n_windows=3, walkers_per_window=2, S=500, lnf_final=1e-3,
+         seed=33, schedule="1/t"),
+], ids=["ising8", "ea3_4", "potts6_1t"])
+def test_checkpoint_resume_bitexact(gpu, orc, tmp_path, kw):
+    """A run saved after some rounds and loaded again continues exactly as the
+    saved run and as the oracle do, through convergence."""
+    kw = _with_couplings(kw)
+    g, o = _pair(gpu, orc, **kw)
+    g.step(7)
+    o.step(7)
+    path = tmp_path / "run.rewl"
+    g.save(path)
+    r = gpu.Run.load(path)
+    assert_same_state(r, o, "loaded")
+    for rounds in (1, 25):
+        g.step(rounds)
+        r.step(rounds)
+        o.step(rounds)
+        assert_same_state(r, o, f"resumed +{rounds}")
+        assert_same_state(g, o, f"original +{rounds}")
+    ok, _ = r.run()
+    assert ok and o.run()
+    assert_same_state(r, o, "resumed converged")
+    lr, lo_ = r.lng(), o.lng()
+    fin = np.isfinite(lo_)
+    assert np.array_equal(lr[fin].view(np.uint64), lo_[fin].view(np.uint64))
+    # a flipped byte is caught by the checksum
+    data = bytearray(path.read_bytes())
+    data[len(data) // 2] ^= 0x40
+    bad = tmp_path / "bad.rewl"
+    bad.write_bytes(bytes(data))
+    with pytest.raises(gpu.RewlError) as e:
+        gpu.Run.load(bad)
+    assert e.value.code == -5
+
+
 def test_ising8_full_run_bitexact(gpu, orc):
     """The small Ising workload run to convergence: same rounds, same stitched ln g."""
     p = run_params("ising8", seed=2)
