@@ -254,6 +254,17 @@ template <> struct kFirstLanes<64> { static constexpr uint64_t value = 1ull; };
 
 __device__ __forceinline__ double pick(bool c, double a, double b) { return c ? a : b; }
 
+// bins one move can reach (largest |dE| / energy step): Ising and the 2D glass
+// 2, the 3D glass 3, Potts 4
+template <int MODEL> struct kReach {
+    static constexpr int value = (MODEL == kPotts) ? 4 : (MODEL == kEA3 ? 3 : 2);
+};
+// whether a recomputed move picks its target among preloaded bins (cheaper
+// than a second LDS round trip up to 7 candidates)
+template <int MODEL> struct kCandidates {
+    static constexpr bool value = MODEL != kPotts;
+};
+
 // sum over the G aligned lanes of a walker group
 template <int G>
 __device__ __forceinline__ unsigned int group_sum(unsigned int v)
@@ -460,13 +471,41 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 double gn = pick(d == 0, gcur, gnx);
                 if (fmask & (kFirstLanes<G>::value << j)) {
                     // some group's attempt j is flagged: every group recomputes
-                    // from its current spins, the flagged ones keep the result
+                    // from its current spins, the flagged ones keep the result.
+                    // The ln g of every bin one move can reach is loaded
+                    // together with the spins (one LDS round trip, not two);
+                    // with one walker per wave the neighbours come from the
+                    // lane that drew the attempt.
                     const int s = (int)(r0.sp_off - sp_base);
-                    const Nbrs nb = nbrs_of<MODEL>(s, a);
+                    Nbrs nb;
+                    if (G == kWave) {
+                        nb.rt = __builtin_amdgcn_readlane(cur.nb.rt, j);
+                        nb.lf = __builtin_amdgcn_readlane(cur.nb.lf, j);
+                        nb.dn = __builtin_amdgcn_readlane(cur.nb.dn, j);
+                        nb.up = __builtin_amdgcn_readlane(cur.nb.up, j);
+                        nb.fw = (MODEL == kEA3) ? __builtin_amdgcn_readlane(cur.nb.fw, j) : s;
+                        nb.bk = (MODEL == kEA3) ? __builtin_amdgcn_readlane(cur.nb.bk, j) : s;
+                    } else {
+                        nb = nbrs_of<MODEL>(s, a);
+                    }
+                    constexpr int R = kReach<MODEL>::value;
+                    double cand[2 * R + 1];
+                    if (kCandidates<MODEL>::value) {
+#pragma unroll
+                        for (int c = 0; c <= 2 * R; ++c)
+                            cand[c] = ld(baddr + (uint32_t)((c - R) * 8));
+                    }
                     const int o2 = sp[s];
                     const int n2 = new_state<MODEL>(o2, (r0.flags >> 16) & 0x7Fu, q);
                     const int d2 = delta_e<MODEL>(sp, J_s, s, nb, o2, n2) * ADDR_PER_E;
-                    const double g2 = ld(baddr + (uint32_t)d2);
+                    double g2;
+                    if (kCandidates<MODEL>::value) {
+                        g2 = cand[0];
+#pragma unroll
+                        for (int c = 1; c <= 2 * R; ++c) g2 = pick(d2 == (c - R) * 8, cand[c], g2);
+                    } else {
+                        g2 = ld(baddr + (uint32_t)d2);
+                    }
                     const bool f = (r0.flags & 0x80000000u) != 0;
                     old = f ? o2 : old;
                     nw = f ? n2 : nw;
