@@ -106,6 +106,9 @@ CASES = [
                    seed=13)),
     ("ea3_3_odd", dict(model="ea3", L=3, n_windows=2, walkers_per_window=3, S=130,
                        lnf_final=1e-2, seed=14)),
+    # one window: no exchange partner, plain WL with m walkers
+    ("ising6_h1", dict(model="ising", L=6, n_windows=1, walkers_per_window=2, S=300,
+                       lnf_final=1e-2, seed=15)),
 ]
 
 
@@ -228,6 +231,23 @@ def test_checkpoint_resume_bitexact(gpu, orc, tmp_path, kw):
     with pytest.raises(gpu.RewlError) as e:
         gpu.Run.load(bad)
     assert e.value.code == -5
+
+
+def test_largest_lattice_bitexact(gpu, orc):
+    """The largest square lattice one walker's window fits in a CU's LDS with
+    32 windows (Ising 120x120: 151.6 KB), two rounds against the oracle; one
+    size up is refused."""
+    kw = dict(model="ising", L=120, n_windows=32, walkers_per_window=1, S=2000, seed=16)
+    g = gpu.Run(**kw)
+    o = orc.Run(**kw, n_threads=0)
+    print("case: ising 120x120, 32 windows x 1", flush=True)
+    assert_same_state(g, o, "start-up")
+    g.step(2)
+    o.step(2)
+    assert_same_state(g, o, "2 rounds")
+    g.close()
+    with pytest.raises(gpu.RewlError):
+        gpu.Run("ising", 128, n_windows=32, walkers_per_window=1)
 
 
 def test_ising8_full_run_bitexact(gpu, orc):
