@@ -1526,13 +1526,14 @@ int rewl_selftest_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out
 {
     if (n <= 0 || !ctr || !key || !out) return fail(REWL_EINVAL, "bad arguments");
     uint32_t *dc = nullptr, *dout = nullptr;
-    HIP_TRY(hipMalloc(&dc, (size_t)n * 16));
-    HIP_TRY(hipMalloc(&dout, (size_t)n * 16));
-    HIP_TRY(hipMemcpy(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice));
-    int rc = rewl_launch_selftest_philox(dc, key[0], key[1], dout, n);
-    if (!rc) HIP_TRY(hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost));
-    (void)hipFree(dc);
-    (void)hipFree(dout);
+    hipError_t e = hipMalloc(&dc, (size_t)n * 16);
+    if (e == hipSuccess) e = hipMalloc(&dout, (size_t)n * 16);
+    if (e == hipSuccess) e = hipMemcpy(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice);
+    int rc = (e == hipSuccess) ? rewl_launch_selftest_philox(dc, key[0], key[1], dout, n) : 0;
+    if (e == hipSuccess && !rc) e = hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost);
+    if (dc) (void)hipFree(dc);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) return hip_fail(e, "selftest");
     return rc ? fail(rc, "selftest launch failed") : REWL_OK;
 }
 
@@ -1541,13 +1542,14 @@ int rewl_selftest_ln_u(const uint32_t *words, double *out, int n)
     if (n <= 0 || !words || !out) return fail(REWL_EINVAL, "bad arguments");
     uint32_t *dw = nullptr;
     double *dout = nullptr;
-    HIP_TRY(hipMalloc(&dw, (size_t)n * 8));
-    HIP_TRY(hipMalloc(&dout, (size_t)n * 8));
-    HIP_TRY(hipMemcpy(dw, words, (size_t)n * 8, hipMemcpyHostToDevice));
-    int rc = rewl_launch_selftest_ln_u(dw, dout, n);
-    if (!rc) HIP_TRY(hipMemcpy(out, dout, (size_t)n * 8, hipMemcpyDeviceToHost));
-    (void)hipFree(dw);
-    (void)hipFree(dout);
+    hipError_t e = hipMalloc(&dw, (size_t)n * 8);
+    if (e == hipSuccess) e = hipMalloc(&dout, (size_t)n * 8);
+    if (e == hipSuccess) e = hipMemcpy(dw, words, (size_t)n * 8, hipMemcpyHostToDevice);
+    int rc = (e == hipSuccess) ? rewl_launch_selftest_ln_u(dw, dout, n) : 0;
+    if (e == hipSuccess && !rc) e = hipMemcpy(out, dout, (size_t)n * 8, hipMemcpyDeviceToHost);
+    if (dw) (void)hipFree(dw);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) return hip_fail(e, "selftest");
     return rc ? fail(rc, "selftest launch failed") : REWL_OK;
 }
 
