@@ -301,7 +301,11 @@ class Run(RunView):
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be gone
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def step(self, rounds):
         _check(lib().rewl_step(self._h, int(rounds)), "rewl_step")
@@ -389,7 +393,11 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be gone
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __getitem__(self, i):
         return self._views[i]
@@ -449,7 +457,11 @@ class Server:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be gone
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def submit(self, **kw):
         p, J = make_params(**kw)
