@@ -23,7 +23,9 @@
  *    valid until the next call on the same thread);
  *  - host pointers are read or written only during the call and stay owned by
  *    the caller; the library copies what it keeps;
- *  - a handle is used by one host thread at a time;
+ *  - a handle is used by one host thread at a time: a call that would advance
+ *    or read a run, batch or server while another thread is inside such a call
+ *    on it returns REWL_EBUSY (step, run, done, get_lng, save, server tick);
  *  - all device work runs on the stream given at creation (NULL: the null
  *    stream); functions that return host data synchronise that stream.
  * Every step of the method runs in this library's HIP kernels (sweep, flatness
@@ -48,7 +50,7 @@ enum {
     REWL_EDEVICE = -3,  /* a HIP call failed */
     REWL_EINIT = -4,    /* a walker could not be brought into its window */
     REWL_ECORRUPT = -5, /* state failed a consistency check */
-    REWL_EBUSY = -6,    /* server has no free capacity */
+    REWL_EBUSY = -6,    /* handle in use by another host thread, or no capacity */
     REWL_ESTITCH = -7   /* a window overlap holds no commonly visited bin */
 };
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -249,6 +250,23 @@ struct rewl_batch {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
     hipStream_t cap_stream = nullptr; // private stream the graph is captured on
+    std::atomic<bool> busy{false};    // a host thread is inside a call on this batch
+};
+
+// Claims a batch for one host thread for the duration of a call; a second
+// thread entering meanwhile gets REWL_EBUSY.
+struct Claim {
+    std::atomic<bool> *flag = nullptr;
+    explicit Claim(rewl_batch *b)
+    {
+        bool expect = false;
+        if (b && b->busy.compare_exchange_strong(expect, true)) flag = &b->busy;
+    }
+    ~Claim()
+    {
+        if (flag) flag->store(false);
+    }
+    explicit operator bool() const { return flag != nullptr; }
 };
 
 namespace {
@@ -827,6 +845,8 @@ const char kMagic[8] = {'R', 'E', 'W', 'L', 'S', 'A', 'V', '1'};
 int rewl_save(rewl_ctx *h, const char *path)
 {
     if (!h || !path) return fail(REWL_EINVAL, "bad handle or path");
+    Claim c(h->batch);
+    if (h->batch && !c) return fail(REWL_EBUSY, "the run is in use by another thread");
     hipStream_t stream = h->batch ? h->batch->stream : nullptr;
     std::vector<char> slab(h->l.total);
     hipError_t e = hipStreamSynchronize(stream);
@@ -956,6 +976,8 @@ int rewl_create(rewl_ctx **out, int model, int L, int q, const int8_t *couplings
 int rewl_step(rewl_ctx *h, int64_t rounds)
 {
     if (!h || !h->own_batch) return fail(REWL_EINVAL, "bad handle (runs of a batch step with it)");
+    Claim c(h->batch);
+    if (!c) return fail(REWL_EBUSY, "the run is in use by another thread");
     return batch_step(h->batch, rounds);
 }
 
@@ -974,6 +996,8 @@ int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches)
 int rewl_run(rewl_ctx *h, int64_t max_rounds, int64_t *rounds_done)
 {
     if (!h || !h->own_batch) return fail(REWL_EINVAL, "bad handle (runs of a batch run with it)");
+    Claim c(h->batch);
+    if (!c) return fail(REWL_EBUSY, "the run is in use by another thread");
     bool done = false;
     int rc = batch_run(h->batch, max_rounds, &done);
     if (rc) return rc;
@@ -1137,6 +1161,8 @@ int rewl_get_lng(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t
                  int64_t *e_step)
 {
     if (!h) return fail(REWL_EINVAL, "bad handle");
+    Claim claim(h->batch);
+    if (h->batch && !claim) return fail(REWL_EBUSY, "the run is in use by another thread");
     if (n_bins) *n_bins = h->g.B;
     if (e_min) *e_min = h->g.e_min;
     if (e_step) *e_step = h->g.step;
@@ -1164,6 +1190,8 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
                   uint64_t *accepts, uint64_t *ex_prop, uint64_t *ex_acc)
 {
     if (!h) return fail(REWL_EINVAL, "bad handle");
+    Claim claim(h->batch);
+    if (h->batch && !claim) return fail(REWL_EBUSY, "the run is in use by another thread");
     if (n_bins) *n_bins = h->g.B;
     if (e_min) *e_min = h->g.e_min;
     if (e_step) *e_step = h->g.step;
@@ -1261,12 +1289,16 @@ int rewl_batch_set_graph(rewl_batch *b, int rounds_per_graph)
 int rewl_batch_step(rewl_batch *b, int64_t rounds)
 {
     if (!b) return fail(REWL_EINVAL, "bad batch");
+    Claim c(b);
+    if (!c) return fail(REWL_EBUSY, "the batch is in use by another thread");
     return batch_step(b, rounds);
 }
 
 int rewl_batch_run(rewl_batch *b, int64_t max_rounds, int64_t *rounds_issued)
 {
     if (!b) return fail(REWL_EINVAL, "bad batch");
+    Claim c(b);
+    if (!c) return fail(REWL_EBUSY, "the batch is in use by another thread");
     bool done = false;
     int rc = batch_run(b, max_rounds, &done);
     if (rc) return rc;
@@ -1277,6 +1309,8 @@ int rewl_batch_run(rewl_batch *b, int64_t max_rounds, int64_t *rounds_issued)
 int rewl_batch_done(rewl_batch *b, int *flags, int cap)
 {
     if (!b || !flags) return fail(REWL_EINVAL, "bad arguments");
+    Claim c(b);
+    if (!c) return fail(REWL_EBUSY, "the batch is in use by another thread");
     std::vector<int> f;
     int rc = batch_done(b, f);
     if (rc) return rc;
@@ -1470,6 +1504,8 @@ int rewl_server_tick(rewl_server *s, int *n_running, int *n_queued)
 {
     if (!s) return fail(REWL_EINVAL, "bad server");
     rewl_batch *b = s->batch;
+    Claim c(b);
+    if (!c) return fail(REWL_EBUSY, "the server is in use by another thread");
     int rc = server_retire(s);
     if (!rc) rc = server_admit(s, b->P > 0 ? b->P : 1);
     if (!rc) rc = batch_step(b, s->rounds_per_tick);

@@ -250,6 +250,36 @@ def test_largest_lattice_bitexact(gpu, orc):
         gpu.Run("ising", 128, n_windows=32, walkers_per_window=1)
 
 
+def test_concurrent_use_is_refused(gpu):
+    """A second host thread calling into a run while the first is stepping it
+    gets REWL_EBUSY; the run is unaffected and usable afterwards."""
+    import threading
+    import time
+
+    r = gpu.Run("ising", 32, n_windows=16, walkers_per_window=4, seed=41)
+    r.step(1)
+    errors = []
+
+    def long_step():
+        try:
+            r.run(300)         # ~0.3 s: rounds in chunks, waiting on each
+        except gpu.RewlError as e:
+            errors.append(e)
+
+    th = threading.Thread(target=long_step)
+    th.start()
+    time.sleep(0.05)
+    with pytest.raises(gpu.RewlError) as e:
+        r.step(1)
+    assert e.value.code == -6
+    th.join()
+    assert not errors
+    assert r.info()["rounds"] == 301
+    r.step(1)
+    assert r.info()["rounds"] == 302
+    r.close()
+
+
 def test_ising8_full_run_bitexact(gpu, orc):
     """The small Ising workload run to convergence: same rounds, same stitched ln g."""
     p = run_params("ising8", seed=2)
