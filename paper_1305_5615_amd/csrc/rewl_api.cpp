@@ -771,6 +771,36 @@ void rewl_destroy(rewl_ctx *h)
     // runs of a user batch are released with the batch
 }
 
+}  // extern "C"
+
+static int get_lng_impl(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t *e_min,
+                 int64_t *e_step)
+{
+    if (!h) return fail(REWL_EINVAL, "bad handle");
+    if (n_bins) *n_bins = h->g.B;
+    if (e_min) *e_min = h->g.e_min;
+    if (e_step) *e_step = h->g.step;
+    if (!out) return REWL_OK;
+    if (cap < h->g.B) return fail(REWL_EINVAL, "output capacity below n_bins");
+    const int H = h->p.n_windows, m = h->p.walkers_per_window;
+    std::vector<double> P((size_t)H * h->g.Wmax);
+    for (int k = 0; k < H; ++k) {
+        int rc = d2h(h, P.data() + (size_t)k * h->g.Wmax,
+                     h->l.lng + 8 * (size_t)(k * m) * h->g.Wmax, (size_t)h->g.Wmax);
+        if (rc) return rc;
+    }
+    int rc = stitch(h, P, out);
+    if (rc) return rc;
+    std::vector<int> dn(H);
+    rc = d2h(h, dn.data(), h->l.done, (size_t)H);
+    if (rc) return rc;
+    for (int k = 0; k < H; ++k)
+        if (!dn[k]) return REWL_NOT_CONVERGED;
+    return REWL_OK;
+}
+
+extern "C" {
+
 int rewl_create_ex(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t buffer_bytes,
                    void *hip_stream)
 {
@@ -1163,26 +1193,7 @@ int rewl_get_lng(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t
     if (!h) return fail(REWL_EINVAL, "bad handle");
     Claim claim(h->batch);
     if (h->batch && !claim) return fail(REWL_EBUSY, "the run is in use by another thread");
-    if (n_bins) *n_bins = h->g.B;
-    if (e_min) *e_min = h->g.e_min;
-    if (e_step) *e_step = h->g.step;
-    if (!out) return REWL_OK;
-    if (cap < h->g.B) return fail(REWL_EINVAL, "output capacity below n_bins");
-    const int H = h->p.n_windows, m = h->p.walkers_per_window;
-    std::vector<double> P((size_t)H * h->g.Wmax);
-    for (int k = 0; k < H; ++k) {
-        int rc = d2h(h, P.data() + (size_t)k * h->g.Wmax,
-                     h->l.lng + 8 * (size_t)(k * m) * h->g.Wmax, (size_t)h->g.Wmax);
-        if (rc) return rc;
-    }
-    int rc = stitch(h, P, out);
-    if (rc) return rc;
-    std::vector<int> dn(H);
-    rc = d2h(h, dn.data(), h->l.done, (size_t)H);
-    if (rc) return rc;
-    for (int k = 0; k < H; ++k)
-        if (!dn[k]) return REWL_NOT_CONVERGED;
-    return REWL_OK;
+    return get_lng_impl(h, out, cap, n_bins, e_min, e_step);
 }
 
 int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step, int *n_windows,
@@ -1383,7 +1394,7 @@ int server_retire(rewl_server *s)
         if (!f) continue;
         rewl_server::Finished fin;
         fin.lng.assign((size_t)h->g.B, 0.0);
-        fin.status = rewl_get_lng(h, fin.lng.data(), h->g.B, &fin.n_bins, &fin.e_min, &fin.e_step);
+        fin.status = get_lng_impl(h, fin.lng.data(), h->g.B, &fin.n_bins, &fin.e_min, &fin.e_step);
         std::vector<long long> fr(h->p.n_windows);
         rc = d2h(h, fr.data(), h->l.finish, fr.size());
         if (rc) return rc;
