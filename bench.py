@@ -16,8 +16,9 @@ Reported on one JSON line:
   max_abs_dlng_vs_exact  per step, max |ln g - ln g_exact| over the bins
                 (Ising sizes with a stored exact DOS);
   batched_glasses  256 independent 24x24 +-J glasses, 8 windows x 4 walkers
-                each, in one batch for a fixed number of rounds: attempts/s and
-                the sweep kernel's roofline (same definition as below);
+                each, in one batch, walkers per wave and attempts between
+                exchanges autotuned: attempts/s over a fixed number of attempts
+                and the sweep kernel's roofline (same definition as below);
   roofline      the sweep kernel's VALU work per attempt times its attempts,
                 over its own time measured with HIP events recorded on the run's
                 stream around each sweep launch, against the MI355X vector-ALU
@@ -167,31 +168,55 @@ def exact_error(p, lng):
     return float(np.abs(lng[fin] - ref[fin]).max())
 
 
-def gpu_glasses(rewl, n_runs, rounds, candidates=(4, 8)):
+def gpu_glasses(rewl, n_runs, rounds, candidates=(4, 8), s_candidates=(1000, 10_000, 100_000)):
     """The batched glass workload: n_runs independent 24x24 +-J instances in one
-    batch, a fixed number of rounds after start-up, walkers per wave tuned over
-    `candidates`.  Returns throughput and the sweep kernel's own time."""
+    batch.  The autotuner picks walkers per wave from `candidates` and attempts
+    per walker between exchanges from `s_candidates` by attempts/s over the same
+    number of attempts (4e4 per walker) each; then `rounds` x 1e4 attempts per
+    walker are timed at the chosen setting.  Returns throughput, the setting and
+    the sweep kernel's own time."""
     import torch
 
     from workloads import run_params
 
-    runs = [run_kwargs(run_params("ea24", seed=1 + i)) for i in range(n_runs)]
-    P = autotune(rewl, [run_params("ea24", seed=1 + i) for i in range(n_runs)], candidates,
-                 rounds=4)
-    b = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
+    def make(P, S):
+        runs = [dict(run_kwargs(run_params("ea24", seed=1 + i)), S=S) for i in range(n_runs)]
+        return rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
+
+    def measure(b, S, attempts_per_walker):
+        b.step(1)
+        torch.cuda.synchronize()
+        a0 = sum(b[i].info()["attempts"] for i in range(n_runs))
+        t0 = time.perf_counter()
+        b.step(max(1, attempts_per_walker // S))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return (sum(b[i].info()["attempts"] for i in range(n_runs)) - a0) / dt
+
+    best, best_rate = None, -1.0
+    for S in s_candidates:
+        for P in candidates:
+            b = make(P, S)
+            rate = measure(b, S, 40_000)
+            b.close()
+            log(f"autotune: glasses P={P} S={S}: {rate / 1e9:.2f} G attempts/s")
+            if rate > best_rate:
+                best, best_rate = (P, S), rate
+    P, S = best
+    b = make(P, S)
     b.set_timing(True)
     b.step(1)
     torch.cuda.synchronize()
     a0 = sum(b[i].info()["attempts"] for i in range(n_runs))
     ms0, n0 = b.timing()
     t0 = time.perf_counter()
-    b.step(rounds)
+    b.step(max(1, rounds * 10_000 // S))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms, n = b.timing()
     att = sum(b[i].info()["attempts"] for i in range(n_runs)) - a0
     b.close()
-    return dict(P=P, attempts=att, wall=wall, sweep_ms=ms - ms0, launches=n - n0)
+    return dict(P=P, S=S, attempts=att, wall=wall, sweep_ms=ms - ms0, launches=n - n0)
 
 
 def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
@@ -605,17 +630,19 @@ def main():
         ach = VALU_SLOTS_PER_ATTEMPT["ea"] * g["attempts"] / (g["sweep_ms"] * 1e-3) / 1e12
         out["batched_glasses"] = {
             "workload": f"{args.glasses} independent 2D +-J EA glasses L=24, 8 windows x 4 "
-                        f"walkers each, {args.glass_rounds} rounds of 1e4 attempts/walker, "
+                        f"walkers each, {args.glass_rounds * 10_000} attempts/walker timed, "
                         "one batch",
-            "walkers_per_wave": g["P"], "value": g["attempts"] / g["wall"],
+            "walkers_per_wave": g["P"], "attempts_per_round": g["S"],
+            "value": g["attempts"] / g["wall"],
             "unit": "attempts/s",
             "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
                          "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
+                         # state in and out once per launch: the same bytes at any S
                          "traffic": profiled_traffic(f"ea24x{args.glasses}_P{g['P']}"),
                          "kernel": f"sweep_kernel<{g['P']}>",
                          "sweep_avg_us": 1e3 * g["sweep_ms"] / max(g["launches"], 1),
                          "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT["ea"]}}
-        log(f"glasses: {args.glasses} runs, P={g['P']}, "
+        log(f"glasses: {args.glasses} runs, P={g['P']}, S={g['S']}, "
             f"{g['attempts'] / g['wall'] / 1e9:.2f} G attempts/s")
     if not args.no_cpu:
         p = dict(run_params(args.workload, seed=1))
