@@ -52,6 +52,47 @@ def test_footprint_validates_on_host(rewl):
         rewl.footprint(model="ising", L=128, n_windows=1)
 
 
+def test_validation_matches_oracle(rewl, oracle_lib):
+    """Every parameter set the oracle refuses, the library refuses too (host
+    validation, no GPU): empty window sets, degenerate overlaps and flatness,
+    non-positive ln f, zero attempts, unknown schedule, bad couplings, sizes
+    out of range, inconsistent explicit windows."""
+    from workloads import ea3_couplings, ea_couplings
+
+    J = ea_couplings(6, 1)
+    bad_J = J.copy()
+    bad_J[3] = 2
+    lo, hi = oracle_lib.partition(37, 3, 0.75)
+    bad_hi = hi.copy()
+    bad_hi[0] = lo[1]                  # windows 0 and 1 would share one bin
+    cases = [
+        dict(model="ising", L=6, n_windows=0),
+        dict(model="ising", L=6, overlap=0.0),
+        dict(model="ising", L=6, flatness=0.0),
+        dict(model="ising", L=6, flatness=1.5),
+        dict(model="ising", L=6, lnf_final=-1.0),
+        dict(model="ising", L=6, lnf_init=0.0),
+        dict(model="ising", L=6, S=0),
+        dict(model="ea", L=6, couplings=bad_J),
+        dict(model="ea3", L=33, couplings=ea3_couplings(33, 1)),
+        dict(model="ea3", L=1, couplings=np.ones(3, np.int8)),
+        dict(model="ising", L=6, n_windows=3, windows=(lo, bad_hi)),
+        dict(model="ising", L=6, e_min=40, e_max=40),
+    ]
+    for kw in cases:
+        with pytest.raises(oracle_lib.OracleError):
+            oracle_lib.Run(**kw)
+        with pytest.raises(rewl.RewlError) as e:
+            rewl.footprint(**kw)
+        assert e.value.code == -1, kw
+    # and the same explicit windows, when valid, are accepted by both
+    rewl.footprint(model="ising", L=6, n_windows=3, windows=(lo, hi))
+    oracle_lib.Run(model="ising", L=6, n_windows=3, windows=(lo, hi))
+    with pytest.raises(rewl.RewlError):
+        rewl.footprint(model="ising", L=6, schedule="1/t", n_windows=3,
+                       windows=(lo[:2], hi[:2]))
+
+
 def test_footprint_grows_with_walkers(rewl):
     a, _ = rewl.footprint(model="potts", L=64, q=10, n_windows=32, walkers_per_window=8)
     b, _ = rewl.footprint(model="potts", L=64, q=10, n_windows=32, walkers_per_window=4)

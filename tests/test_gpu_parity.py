@@ -312,6 +312,18 @@ def test_full_size_rounds_bitexact(gpu, orc, name, rounds):
     assert_same_state(g, o, f"{name} after {rounds} rounds")
 
 
+def test_zero_rounds_change_nothing(gpu, orc):
+    """Stepping or running zero rounds leaves a run as it was."""
+    kw = dict(model="ising", L=8, n_windows=4, walkers_per_window=2, S=500, seed=51)
+    g, o = _pair(gpu, orc, **kw)
+    g.step(3)
+    o.step(3)
+    g.step(0)
+    ok, rounds = g.run(0)
+    assert not ok and rounds == 3
+    assert_same_state(g, o, "after zero rounds")
+
+
 def test_invalid_arguments_rejected(gpu):
     with pytest.raises(gpu.RewlError) as e:
         gpu.Run("ising", 2)
