@@ -89,13 +89,13 @@ struct alignas(16) Prop {
     uint32_t flags;    // new state (8 bits) | old state << 8 | Potts r1 << 16
                        // | 1 << 31 if an earlier proposal of the block touches
                        //   the site or one of its neighbours
-    uint32_t site;
+    uint32_t site;     // the site (unused by the pass; pads to 32 bytes)
 };
 
 // LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:
 // ln g (8 (W + 8), with 4 guard bins on either side), H (4 W), G + 2 staged
-// proposals, per-site G-bit proposal masks (G/8 N), spins (N), each rounded up
-// to 16 bytes.
+// proposals, G per-step bin records, per-site G-bit proposal masks (G/8 N),
+// spins (N), each rounded up to 16 bytes.
 inline size_t lds_up16(size_t x) { return (x + 15) & ~(size_t)15; }
 inline size_t sweep_walker_lds(int W, int N, int G)
 {
@@ -103,6 +103,7 @@ inline size_t sweep_walker_lds(int W, int N, int G)
     b += lds_up16((size_t)(W + 8) * 8);
     b += lds_up16((size_t)W * 4);
     b += (size_t)(G + 2) * sizeof(Prop);
+    b += lds_up16((size_t)G * 4);
     b += lds_up16((size_t)N * (size_t)(G / 8));
     b += lds_up16((size_t)N);
     return b;

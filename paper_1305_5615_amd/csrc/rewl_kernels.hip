@@ -277,7 +277,12 @@ __device__ __forceinline__ unsigned int group_sum(unsigned int v)
 // energy change is 8 (Ising, +-J: 2 bins of 4) or 4 (Potts: 4 bins of 1)
 constexpr int kGuard = 4;
 
-template <int MODEL, int P>
+// RP: the per-step bin records (bin | accepted, for the H update at the end
+// of a block) are kept in a register of the lane that drew the attempt rather
+// than stored to LDS.  That costs VALU work per step and saves an LDS store;
+// it measured faster when several waves share a CU's LDS and slower with one
+// wave per CU, so the launcher picks it by the number of waves.
+template <int MODEL, int P, bool RP>
 __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
                                            const BatchDev &bd, unsigned char *smem)
 {
@@ -299,7 +304,9 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     uint32_t *H_s = reinterpret_cast<uint32_t *>(mine + up16((size_t)(bd.max_W + 2 * kGuard) * 8));
     Prop *stage = reinterpret_cast<Prop *>(reinterpret_cast<unsigned char *>(H_s) +
                                            up16((size_t)bd.max_W * 4));
-    TagT *tag = reinterpret_cast<TagT *>(stage + G + 2);
+    uint32_t *post_s = reinterpret_cast<uint32_t *>(stage + G + 2);
+    TagT *tag = reinterpret_cast<TagT *>(reinterpret_cast<unsigned char *>(post_s) +
+                                         up16((size_t)G * 4));
     int8_t *sp = reinterpret_cast<int8_t *>(reinterpret_cast<unsigned char *>(tag) +
                                             up16((size_t)bd.max_N * sizeof(TagT)));
     uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)P * region);
@@ -395,6 +402,8 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     for (long long base = 0; base < S; base += G) {
         const int n = (S - base < G) ? (int)(S - base) : G;
         const bool active = live && gl < n;
+        bool flagged = false;
+        uint32_t post = 0;
         // state-dependent part, against the configuration at the block start
         if (active) {
             const int old = sp[cur.site];
@@ -413,6 +422,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                       ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
             p.site = (uint32_t)cur.site;
             stage[gl] = p;
+            flagged = (seen & (bit - 1ull)) != 0;
         } else {
             // records past the last attempt: a zero move, read ahead only
             stage[gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
@@ -430,7 +440,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             for (int piece = 0; piece < 8; ++piece) draw_piece(nxt, piece);
         }
         // flagged attempts of the block, one bit per lane (wave-uniform)
-        const uint64_t fmask = __builtin_amdgcn_ballot_w64(active && (stage[gl].flags >> 31));
+        const uint64_t fmask = __builtin_amdgcn_ballot_w64(flagged);
         if (live) {
             // In-order pass, executed identically by every lane of the group.
             // The only branch is taken when some group of the wave has a
@@ -469,7 +479,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 int nw = (int)(int8_t)(r0.flags & 0xFFu);
                 int old = (int)(int8_t)((r0.flags >> 8) & 0xFFu);
                 double gn = pick(d == 0, gcur, gnx);
-                if (fmask & (kFirstLanes<G>::value << j)) {
+                if (__builtin_expect((fmask & (kFirstLanes<G>::value << j)) != 0, 0)) {
                     // some group's attempt j is flagged: every group recomputes
                     // from its current spins, the flagged ones keep the result.
                     // The ln g of every bin one move can reach is loaded
@@ -522,7 +532,10 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 *reinterpret_cast<double *>(smem + baddr) = gcur;
                 smem[r0.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
                 // bin after attempt j and its acceptance, for lane j's H update
-                stage[j].site = baddr | (accept ? 1u : 0u);
+                if constexpr (RP)
+                    post = (gl == j) ? (baddr | (accept ? 1u : 0u)) : post;
+                else
+                    post_s[j] = baddr | (accept ? 1u : 0u);
                 r0 = r1;
                 r1 = r2;
             };
@@ -544,7 +557,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         }
         // H of the block's attempts, one atomic per lane
         if (active) {
-            const uint32_t v = stage[gl].site;
+            const uint32_t v = RP ? post : post_s[gl];
             atomicAdd(&H_s[((v & ~7u) - lng_base) >> 3], 1u);
             acc += v & 1u;
         }
@@ -570,17 +583,17 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     }
 }
 
-template <int P>
+template <int P, bool RP>
 __global__ __launch_bounds__(kWave) void sweep_kernel(BatchDev bd)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const SweepItem it = bd.sweep[blockIdx.x];
     const RunDesc a = bd.runs[it.run];
     switch (a.model) {
-    case kIsing: sweep_body<kIsing, P>(a, it, bd, smem); break;
-    case kPotts: sweep_body<kPotts, P>(a, it, bd, smem); break;
-    case kEA: sweep_body<kEA, P>(a, it, bd, smem); break;
-    default: sweep_body<kEA3, P>(a, it, bd, smem); break;
+    case kIsing: sweep_body<kIsing, P, RP>(a, it, bd, smem); break;
+    case kPotts: sweep_body<kPotts, P, RP>(a, it, bd, smem); break;
+    case kEA: sweep_body<kEA, P, RP>(a, it, bd, smem); break;
+    default: sweep_body<kEA3, P, RP>(a, it, bd, smem); break;
     }
 }
 
@@ -808,19 +821,42 @@ int launch_init_t(const RunDesc &a, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-template <int P>
-int launch_sweep_t(const BatchDev &b, hipStream_t s, size_t lds)
+template <int P, bool RP>
+int launch_sweep_rp(const BatchDev &b, hipStream_t s, size_t lds)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P, RP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kMaxLds) != hipSuccess)
             return -3;
         attr_set = true;
     }
-    hipLaunchKernelGGL(sweep_kernel<P>, dim3(b.n_sweep), dim3(kWave), lds, s, b);
+    hipLaunchKernelGGL((sweep_kernel<P, RP>), dim3(b.n_sweep), dim3(kWave), lds, s, b);
     return 0;
+}
+
+// compute units of the current device (cached per device)
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+template <int P>
+int launch_sweep_t(const BatchDev &b, hipStream_t s, size_t lds)
+{
+    // more waves than compute units: several waves share each LDS
+    if (b.n_sweep > device_cus()) return launch_sweep_rp<P, true>(b, s, lds);
+    return launch_sweep_rp<P, false>(b, s, lds);
 }
 
 }  // namespace

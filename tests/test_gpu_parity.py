@@ -235,7 +235,7 @@ def test_checkpoint_resume_bitexact(gpu, orc, tmp_path, kw):
 
 def test_largest_lattice_bitexact(gpu, orc):
     """The largest square lattice one walker's window fits in a CU's LDS with
-    32 windows (Ising 120x120: 151.6 KB), two rounds against the oracle; one
+    32 windows (Ising 120x120: 151.8 KB), two rounds against the oracle; one
     size up is refused."""
     kw = dict(model="ising", L=120, n_windows=32, walkers_per_window=1, S=2000, seed=16)
     g = gpu.Run(**kw)
@@ -414,6 +414,48 @@ def test_batch_full_size_glasses(gpu, orc):
         o = orc.Run(**runs[i], n_threads=0)
         o.step(2)
         assert_same_state(b[i], o, f"ea24 run {i}")
+    b.close()
+
+
+def _cus():
+    import torch
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def test_batch_more_waves_than_cus_one_walker_per_wave(gpu, orc):
+    """Eight copies (new seeds) of the mixed runs, one walker per wave: more
+    waves than the device has compute units, which selects the sweep form that
+    keeps the per-step bin records in registers; every run equals the oracle."""
+    runs = []
+    for c in range(8):
+        for kw in MIXED:
+            runs.append(_with_couplings(dict(kw, seed=kw["seed"] + 100 * (c + 1))))
+    walkers = sum(kw["n_windows"] * kw["walkers_per_window"] for kw in runs)
+    assert walkers > _cus()
+    print("case: 8 x mixed batch, P=1,", walkers, "waves", flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=1)
+    oracles = [orc.Run(**kw) for kw in runs]
+    for rounds in (1, 5):
+        b.step(rounds)
+        for o in oracles:
+            o.step(rounds)
+        for i, o in enumerate(oracles):
+            assert_same_state(b[i], o, f"many-wave batch run {i}")
+    b.close()
+
+
+def test_batch_full_glass_workload_samples(gpu, orc):
+    """The 256-glass workload as the benchmark times it (8 walkers per wave,
+    1024 waves): 2 rounds, then sampled runs against the oracle."""
+    runs = [_kw(run_params("ea24", seed=1 + s)) for s in range(256)]
+    assert 256 * 32 // 8 > _cus()
+    print("case: 256 x ea24 batch, P=8", flush=True)
+    b = gpu.Batch(runs, walkers_per_wave=8)
+    b.step(2)
+    for i in (0, 101, 255):
+        o = orc.Run(**runs[i], n_threads=0)
+        o.step(2)
+        assert_same_state(b[i], o, f"ea24 run {i} of 256")
     b.close()
 
 
