@@ -102,6 +102,14 @@ def profiled_traffic(tag):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def sweep_kernel_name(P, waves):
+    """The sweep instantiation a launch of `waves` waves runs: the per-step bin
+    records sit in registers when waves outnumber the compute units."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return f"sweep_kernel<{P}, {'true' if waves > cus else 'false'}>"
+
+
 def percentile(xs, q):
     import numpy as np
 
@@ -601,7 +609,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / VALU_PEAK_TOPS if achieved else None,
                 "traffic": profiled_traffic(args.workload),
-                "kernel": "sweep_kernel<1>",
+                "kernel": sweep_kernel_name(1, base["n_windows"] * base["walkers_per_window"]),
                 "sweep_avg_us": 1e3 * sweep_ms / launches if launches else None,
                 "valu_slots_per_attempt": slots}
     out = {
@@ -646,7 +654,7 @@ def main():
                          "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
                          # state in and out once per launch: the same bytes at any S
                          "traffic": profiled_traffic(f"ea24x{args.glasses}_P{g['P']}"),
-                         "kernel": f"sweep_kernel<{g['P']}>",
+                         "kernel": sweep_kernel_name(g["P"], args.glasses * 32 // g["P"]),
                          "sweep_avg_us": 1e3 * g["sweep_ms"] / max(g["launches"], 1),
                          "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT["ea"]}}
         log(f"glasses: {args.glasses} runs, P={g['P']}, S={g['S']}, "

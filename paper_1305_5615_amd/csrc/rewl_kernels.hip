@@ -1,13 +1,14 @@
 // rewl_kernels.hip -- HIP kernels of replica-exchange Wang-Landau for gfx950.
 //
 // One round of every run of a batch is four launches on the batch's stream:
-//   sweep_kernel<P>    one wave per group of P walkers of one run; each
+//   sweep_kernel<P,RP> one wave per group of P walkers of one run; each
 //                      walker's spins, ln g and H live in LDS for the round;
 //                      the walker's 64/P lanes draw 64/P attempts at a time
 //                      (Philox, site, neighbours, ln u, energy change) in
-//                      parallel and one lane per walker then applies them in
-//                      order, which keeps the sequential single-site dynamics
-//                      of the standard WL walk (standard-WL paragraph);
+//                      parallel, then all of them apply the attempts in order,
+//                      identically, which keeps the sequential single-site
+//                      dynamics of the standard WL walk (standard-WL
+//                      paragraph); RP: where the per-step bin records live;
 //   flat_merge_kernel  one work-group per window: flatness of each walker,
 //                      and when all m are flat the mean of their ln g, H reset,
 //                      ln f halved (parallel-scheme paragraph); under the 1/t
