@@ -363,22 +363,6 @@ def served(rewl, args):
                          sizes=args.served_sizes)
     kinds = [r["params"] for r in reqs]
 
-    # plain FIFO
-    t0 = time.perf_counter()
-    fifo_lat, fifo_att = [], 0
-    for r in ([] if args.no_fifo else reqs):
-        now = time.perf_counter() - t0
-        if now < r["arrival"]:
-            time.sleep(r["arrival"] - now)
-        run = rewl.Run(**run_kwargs(r["params"]))
-        run.run()
-        run.lng()
-        fifo_att += run.info()["attempts"]
-        run.close()
-        fifo_lat.append(time.perf_counter() - t0 - r["arrival"])
-    fifo_wall = time.perf_counter() - t0
-    log(f"served: FIFO {len(reqs)} runs in {fifo_wall:.1f} s")
-
     # continuous batching
     # one walker per wave measured best for this stream (p99 8.1 s vs 9.2 s at 2)
     srv = rewl.Server(device_budget_bytes=args.budget_mb << 20,
@@ -387,24 +371,61 @@ def served(rewl, args):
     t0 = time.perf_counter()
     pending = list(range(len(reqs)))
     ids, lat = {}, {}
+    ticks = 0
+    failed = []
     while len(lat) < len(reqs):
         now = time.perf_counter() - t0
         while pending and reqs[pending[0]]["arrival"] <= now:
             i = pending.pop(0)
             ids[srv.submit(**run_kwargs(reqs[i]["params"]))] = i
         running, queued = srv.tick()
+        ticks += 1
+        if ticks % 5000 == 0:
+            log(f"served: {ticks} ticks, {running} running, {queued} queued, {len(lat)} done")
         while True:
             d = srv.next_done()
             if d is None:
                 break
             i = ids[d[0]]
-            srv.result(d[0])
+            try:
+                srv.result(d[0])
+            except rewl.RewlError as e:
+                failed.append(i)
+                log(f"served: request {i} failed: {e}")
             srv.release(d[0])
             lat[i] = time.perf_counter() - t0 - reqs[i]["arrival"]
+            log(f"served: request {i} done, latency {lat[i]:.2f} s ({len(lat)}/{len(reqs)})")
         if running == 0 and queued == 0 and pending:
             time.sleep(max(0.0, reqs[pending[0]]["arrival"] - (time.perf_counter() - t0)))
     srv_wall = time.perf_counter() - t0
     srv.close()
+    ok_lat = [v for k, v in lat.items() if k not in failed]
+    log(f"served: server {len(reqs)} runs in {srv_wall:.1f} s ({len(failed)} failed at start-up), "
+        f"p50 {percentile(ok_lat, 50):.2f} s, p99 {percentile(ok_lat, 99):.2f} s")
+
+    # plain FIFO
+    t0 = time.perf_counter()
+    fifo_lat, fifo_att = [], 0
+    for r in ([] if args.no_fifo else reqs):
+        now = time.perf_counter() - t0
+        if now < r["arrival"]:
+            time.sleep(r["arrival"] - now)
+        try:
+            run = rewl.Run(**run_kwargs(r["params"]))
+        except rewl.RewlError as e:
+            fifo_lat.append(time.perf_counter() - t0 - r["arrival"])
+            log(f"served: FIFO request {len(fifo_lat) - 1} failed: {e}")
+            continue
+        while not run.run(50_000)[0]:
+            log(f"served: FIFO request {len(fifo_lat)}: {run.info()['rounds']} rounds")
+        run.lng()
+        fifo_att += run.info()["attempts"]
+        run.close()
+        fifo_lat.append(time.perf_counter() - t0 - r["arrival"])
+        log(f"served: FIFO request {len(fifo_lat) - 1} done, latency {fifo_lat[-1]:.2f} s")
+    fifo_wall = time.perf_counter() - t0
+    log(f"served: FIFO {len(reqs)} runs in {fifo_wall:.1f} s")
+
     att = fifo_att  # the served runs are bit-identical to the plain ones: same attempts
     if args.no_fifo:
         att = None  # attempts are counted on the plain runs
@@ -413,11 +434,12 @@ def served(rewl, args):
         "requests": len(reqs), "rate_per_s": args.rate, "sizes": args.served_sizes,
         "lnf_final": [1e-3, 1e-4],
         "mix": {m: sum(1 for k in kinds if k["model"] == m) for m in ("ising", "potts", "ea")},
-        "served": {"p50_s": percentile(list(lat.values()), 50),
-                   "p99_s": percentile(list(lat.values()), 99), "wall_s": srv_wall,
-                   "attempts_per_s": att / srv_wall if att else None},
+        "failed_at_start_up": sorted(failed),
+        "served": {"p50_s": percentile(ok_lat, 50), "p99_s": percentile(ok_lat, 99),
+                   "wall_s": srv_wall, "attempts_per_s": att / srv_wall if att else None},
         "fifo": None if args.no_fifo else {
-            "p50_s": percentile(fifo_lat, 50), "p99_s": percentile(fifo_lat, 99),
+            "p50_s": percentile([v for k, v in enumerate(fifo_lat) if k not in failed], 50),
+            "p99_s": percentile([v for k, v in enumerate(fifo_lat) if k not in failed], 99),
             "wall_s": fifo_wall, "attempts_per_s": att / fifo_wall},
         "walkers_per_wave": args.walkers_per_wave or 1,
     }

@@ -279,7 +279,10 @@ void rewl_batch_destroy(rewl_batch *b);
  *    running runs by rounds_per_tick rounds (synchronous in its retire step).
  *  rewl_server_next_done: id of the next finished run (REWL_NOT_CONVERGED when
  *    none) and the rounds it ran.
- *  rewl_server_result: its stitched, normalised ln g (as rewl_get_lng).
+ *  rewl_server_result: its stitched, normalised ln g (as rewl_get_lng).  A
+ *    request whose start-up fails (REWL_EINIT: a walker cannot reach its
+ *    window) is taken off the queue at admission and finishes at once with 0
+ *    rounds; its result returns that code and the other runs go on.
  *  REWL_EBUSY from submit: the run alone exceeds the device budget. */
 typedef struct rewl_server rewl_server;
 int rewl_server_create(rewl_server **out, size_t device_budget_bytes, int walkers_per_wave,

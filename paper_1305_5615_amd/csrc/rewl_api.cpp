@@ -1372,6 +1372,7 @@ struct rewl_server {
         std::vector<double> lng;
         int64_t n_bins, e_min, e_step, rounds;
         int status;
+        std::string what;  // why the run failed (status < 0)
     };
     std::map<int64_t, Finished> results;
     std::vector<int64_t> done_order;    // finished ids not yet popped
@@ -1433,11 +1434,22 @@ int server_admit(rewl_server *s, int want_P)
         if (s->used + q.bytes > s->budget) break;
         Geometry g;
         int rc = validate(&q.p, g);
-        if (rc) return rc;
-        const int P = fit_P(b, want_P, g.Wmax, g.N, model_j_words(q.p.model));
+        const int P = rc ? 1 : fit_P(b, want_P, g.Wmax, g.N, model_j_words(q.p.model));
         if (P == 0) break;
         rewl_ctx *h = nullptr;
-        rc = make_run(&h, &q.p, nullptr, 0, b->stream);
+        if (!rc) rc = make_run(&h, &q.p, nullptr, 0, b->stream);
+        if (rc == REWL_EINIT || rc == REWL_EINVAL) {
+            // the request itself cannot run (a walker cannot reach its
+            // window): it finishes at once with that status, the others go on
+            rewl_server::Finished fin;
+            fin.n_bins = fin.e_min = fin.e_step = fin.rounds = 0;
+            fin.status = rc;
+            fin.what = rewl_last_error();
+            s->results[q.id] = std::move(fin);
+            s->done_order.push_back(q.id);
+            s->queue.erase(s->queue.begin());
+            continue;
+        }
         if (rc) return rc;
         h->batch = b;
         h->id = q.id;
@@ -1545,6 +1557,7 @@ int rewl_server_result(rewl_server *s, int64_t id, double *out, int64_t cap, int
     auto it = s->results.find(id);
     if (it == s->results.end()) return fail(REWL_EINVAL, "unknown or unfinished request id");
     const rewl_server::Finished &f = it->second;
+    if (f.status < 0) return fail(f.status, f.what.c_str());
     if (n_bins) *n_bins = f.n_bins;
     if (e_min) *e_min = f.e_min;
     if (e_step) *e_step = f.e_step;

@@ -496,3 +496,40 @@ def test_server_results_equal_alone(gpu, orc):
         assert np.array_equal(np.isfinite(lg), fin), i
         assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64)), i
     srv.close()
+
+
+def test_server_unstartable_request_finishes_alone(gpu, orc):
+    """A request no walker can start (a +-J window entirely below the ground
+    state) finishes at once with REWL_EINIT, as the oracle refuses it too; the
+    runs around it are unaffected and equal the oracle."""
+    bad = _with_couplings(dict(model="ea", L=8, e_min=-128, e_max=-100, n_windows=2,
+                               walkers_per_window=2, S=1000, lnf_final=1e-2, seed=5))
+    with pytest.raises(Exception):
+        orc.Run(**bad)
+    good = [_with_couplings(kw) for kw in MIXED[:2]]
+    print("case: server with one unstartable request", flush=True)
+    srv = gpu.Server(device_budget_bytes=64 << 20, walkers_per_wave=1, rounds_per_tick=4)
+    ids = [srv.submit(**good[0]), srv.submit(**bad), srv.submit(**good[1])]
+    done = {}
+    ticks = 0
+    while len(done) < 3:
+        srv.tick()
+        while True:
+            d = srv.next_done()
+            if d is None:
+                break
+            done[d[0]] = d[1]
+        ticks += 1
+        assert ticks < 5000
+    assert done[ids[1]] == 0
+    with pytest.raises(gpu.RewlError) as e:
+        srv.result(ids[1])
+    assert e.value.code == -4
+    for rid, kw in ((ids[0], good[0]), (ids[2], good[1])):
+        o = orc.Run(**kw)
+        assert o.run()
+        lg, lo = srv.result(rid), o.lng()
+        fin = np.isfinite(lo)
+        assert np.array_equal(np.isfinite(lg), fin)
+        assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
+    srv.close()

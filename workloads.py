@@ -82,7 +82,7 @@ def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6)
     """Poisson arrivals of REWL requests with a mix of models and sizes.
 
     sizes="full": Ising L in {16,24,32,48,64}; Potts q in 2..10, L in 16..48;
-    +-J L in 16..32; windows 4..32.  sizes="small": the same mix on L <= 16 and
+    +-J L in 16..32 on |E| <= 1.5 N; windows 4..32.  sizes="small": the same mix on L <= 16 and
     4..16 windows, for runs of seconds.  Walkers 2, 4 or 8 per window.  Returns
     a list of dicts with an 'arrival' time in seconds and the run parameters.
     """
@@ -105,6 +105,10 @@ def served_stream(n_requests, rate_per_s, seed=7, lnf_choices=(1e-4, 1e-5, 1e-6)
         h = int(rng.integers(hs[0], hs[1] + 1))
         m = int(rng.choice([2, 4, 8]))
         e_min, e_max = full_range(kind, L)
+        if kind == "ea":
+            # +-J: |E| <= 1.5 N holds every state an instance can reach (the
+            # ground state is near -1.40 N), so no window lies wholly below it
+            e_min, e_max = -(3 * L * L) // 2, (3 * L * L) // 2
         p = dict(model=kind, L=L, q=q, n_windows=h, overlap=0.75, walkers_per_window=m,
                  flatness=0.8, lnf_init=1.0, lnf_final=float(rng.choice(lnf_choices)),
                  S=10_000, e_min=e_min, e_max=e_max, seed=1000 + i)
