@@ -211,10 +211,10 @@ __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
 // group draws attempt t+g (Philox stream 0: site, Potts offset, u -> ln u),
 // computes its energy change against the configuration at the start of the
 // block, and flags it when an earlier proposal of the block hits its site or a
-// neighbour (per-site masks in LDS, set with an atomic OR).  The group's first
-// lane then applies the G attempts in order; a flagged attempt recomputes its
-// energy change from the current spins, every other one uses the precomputed
-// value, so the result is that of the plain sequential walk.
+// neighbour (per-site masks in LDS, set with an atomic OR).  Every lane of the
+// group then applies the G attempts in order, identically; a flagged attempt
+// recomputes its energy change from the current spins, every other one uses
+// the precomputed value, so the result is that of the plain sequential walk.
 template <int MODEL>
 __device__ __forceinline__ int new_state(int old, uint32_t r1, int q)
 {
@@ -430,10 +430,11 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         }
         __syncthreads();
         if (active) tag[cur.site] = (TagT)0;
-        // draws of the next block: with several walkers per wave, spread over
-        // the in-order pass below; with one, whole here (the compiler then
-        // interleaves them with the 64-attempt pass by itself, which measured
-        // faster than the spread)
+        // draws of the next block: with several walkers per wave, in pieces
+        // between the steps of the in-order pass below; with one, whole here.
+        // Either way they do not depend on the pass, and the compiler is free
+        // to place them (it gathers them after the pass; pinning the pieces
+        // between the steps measured no faster)
         constexpr bool kSpread = G < 64;
         DrawSt nxt = draw_start(base + G);
         if (!kSpread) {
