@@ -577,7 +577,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: each REWL run lives on one device and "
-              "this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
+              "the library has no multi-GPU path (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch
