@@ -238,6 +238,7 @@ def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
     b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=walkers_per_wave,
                    graph_rounds=graph_rounds)
     done_at = [None] * len(params)
+    lngs = [None] * len(params)
     issued, chunk = 0, 64
     while issued < max_rounds:
         b.step(chunk)
@@ -245,7 +246,7 @@ def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
         d = b.done()
         for i in np.nonzero(d)[0]:
             if done_at[i] is None:
-                b[int(i)].lng()
+                lngs[i] = b[int(i)].lng()
                 done_at[i] = time.perf_counter() - t0
         if d.all():
             break
@@ -255,7 +256,7 @@ def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
     wall = time.perf_counter() - t0
     attempts = sum(b[i].info()["attempts"] for i in range(len(params)))
     b.close()
-    return dict(wall=wall, attempts=attempts, done_at=done_at)
+    return dict(wall=wall, attempts=attempts, done_at=done_at, lng=lngs)
 
 
 def autotune(rewl, params, candidates=(1, 2, 4, 8), rounds=6):
@@ -660,6 +661,17 @@ def main():
                           "time_to_dos_s": {"p50": percentile(dts, 50),
                                             "p99": percentile(dts, 99)},
                           "seeds": list(range(1, args.batch + 1))}
+        import numpy as np
+
+        done_lng = [x for x in bres["lng"] if x is not None]
+        errs = [exact_error(params[i], x) for i, x in enumerate(bres["lng"]) if x is not None]
+        if len(done_lng) >= 2 and all(e is not None for e in errs):
+            # independent runs: the mean ln g and its jackknife error bar
+            mean, jk = rewl.jackknife(np.array(done_lng))
+            fin = np.isfinite(mean)
+            out["batched"]["max_abs_dlng_vs_exact"] = {
+                "per_run": errs, "mean_of_runs": exact_error(params[0], mean),
+                "max_jackknife_error_of_mean": float(np.nanmax(jk[fin]))}
         log(f"batched: {args.batch} runs, P={P}, {bres['wall']:.1f} s, "
             f"{bres['attempts'] / bres['wall'] / 1e9:.3f} G attempts/s")
     if args.glasses > 0:
