@@ -162,3 +162,36 @@ def test_load_rejects_non_checkpoints(tmp_path):
     # a valid tag with a wrong checksum
     junk.write_bytes(b"REWLSAV1" + bytes(64))
     assert rewl.lib().rewl_load(C.byref(h), str(junk).encode(), None, 0, None) == -5
+
+
+@pytest.mark.parametrize("sizes", ["small", "full"])
+def test_served_streams_are_valid(rewl, sizes):
+    """The served benchmark's request streams: arrivals increase, all three
+    models appear, every request passes host validation and fits a CU's LDS,
+    and +-J requests stay within |E| <= 1.5 N (to the integer below for odd N)."""
+    import bench
+    from workloads import served_stream
+
+    reqs = served_stream(48, 4.0, seed=7, lnf_choices=(1e-3, 1e-4), sizes=sizes)
+    arr = [r["arrival"] for r in reqs]
+    assert all(b > a for a, b in zip(arr, arr[1:]))
+    assert {r["params"]["model"] for r in reqs} == {"ising", "potts", "ea"}
+    for r in reqs:
+        p = r["params"]
+        dev, lds = rewl.footprint(**bench.run_kwargs(p))
+        assert dev > 0 and 0 < lds <= 160 * 1024
+        if p["model"] == "ea":
+            N = p["L"] ** 2
+            assert -1.5 * N - 0.5 <= p["e_min"] < p["e_max"] <= 1.5 * N
+
+
+def test_oracle_refuses_an_unstartable_glass(oracle_lib):
+    """A +-J window wholly below any reachable energy (8x8, E <= -100 where
+    the ground state is near -90) fails the start-up with REWL_EINIT (-4) in
+    the oracle, which the served GPU test relies on."""
+    from workloads import ea_couplings
+
+    with pytest.raises(oracle_lib.OracleError) as e:
+        oracle_lib.Run(model="ea", L=8, couplings=ea_couplings(8, 5), e_min=-128, e_max=-100,
+                       n_windows=2, walkers_per_window=2, S=1000, lnf_final=1e-2, seed=5)
+    assert e.value.code == -4
