@@ -21,6 +21,8 @@
 // window) is init_kernel.  Compiled with -ffp-contract=off (see rewl_device.h).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "rewl_device.h"
 #include "rewl_internal.h"
 
@@ -826,13 +828,16 @@ int launch_init_t(const RunDesc &a, hipStream_t s)
 template <int P, bool RP>
 int launch_sweep_rp(const BatchDev &b, hipStream_t s, size_t lds)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
+    // the LDS limit is raised once per device the kernel runs on
+    static std::atomic<bool> attr_set[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -3;
+    if (!attr_set[dev].load()) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P, RP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kMaxLds) != hipSuccess)
             return -3;
-        attr_set = true;
+        attr_set[dev].store(true);
     }
     hipLaunchKernelGGL((sweep_kernel<P, RP>), dim3(b.n_sweep), dim3(kWave), lds, s, b);
     return 0;
@@ -841,16 +846,16 @@ int launch_sweep_rp(const BatchDev &b, hipStream_t s, size_t lds)
 // compute units of the current device (cached per device)
 int device_cus()
 {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    if (cus[dev] == 0) {
+    if (cus[dev].load() == 0) {
         int n = 0;
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
-        cus[dev] = n;
+        cus[dev].store(n);
     }
-    return cus[dev];
+    return cus[dev].load();
 }
 
 template <int P>
