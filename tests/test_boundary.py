@@ -195,3 +195,19 @@ def test_oracle_refuses_an_unstartable_glass(oracle_lib):
         oracle_lib.Run(model="ea", L=8, couplings=ea_couplings(8, 5), e_min=-128, e_max=-100,
                        n_windows=2, walkers_per_window=2, S=1000, lnf_final=1e-2, seed=5)
     assert e.value.code == -4
+
+
+def test_no_cpu_fallback_without_a_gpu(rewl):
+    """Without a visible GPU, runs, batches and servers refuse to exist: there
+    is no CPU path behind the binding."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    kw = dict(model="ising", L=8, n_windows=2, walkers_per_window=1)
+    with pytest.raises(RuntimeError, match="no GPU"):
+        rewl.Run(**kw)
+    with pytest.raises(RuntimeError, match="no GPU"):
+        rewl.Batch([kw], walkers_per_wave=1)
+    with pytest.raises(RuntimeError, match="no GPU"):
+        rewl.Server(device_budget_bytes=1 << 20)
