@@ -325,14 +325,16 @@ def profile(rewl, args, run_params):
     """Fixed rounds of one run (or of a batch) after start-up, for profilers."""
     import torch
 
+    over = {"S": args.attempts_per_round} if args.attempts_per_round else {}
     if args.batch > 1 and args.walkers_per_wave > 0:
-        runs = [run_kwargs(run_params(args.workload, seed=1 + i)) for i in range(args.batch)]
+        runs = [run_kwargs(run_params(args.workload, seed=1 + i, **over))
+                for i in range(args.batch)]
         P = args.walkers_per_wave
         r = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
         label = f"{len(runs)} x {args.workload}, P={P}"
         views = [r[i] for i in range(len(runs))]
     else:
-        r = rewl.Run(**run_kwargs(run_params(args.workload, seed=1)))
+        r = rewl.Run(**run_kwargs(run_params(args.workload, seed=1, **over)))
         label = args.workload
         views = [r]
     r.set_timing(True)
@@ -559,6 +561,8 @@ def main():
                     help="batched glass leg: rounds timed after start-up")
     ap.add_argument("--rounds", type=int, default=0,
                     help="profile mode: run this many rounds after start-up, then exit")
+    ap.add_argument("--attempts-per-round", type=int, default=0,
+                    help="profile mode: attempts per walker between exchanges (0: the workload's)")
     ap.add_argument("--served", type=int, default=0,
                     help="served mode: this many Poisson-arriving requests")
     ap.add_argument("--rate", type=float, default=2.0, help="served mode: arrivals per second")
