@@ -12,7 +12,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rewl_oracle.c")
-LIB = os.path.join(HERE, "librewl_oracle.so")
+# REWL_ORACLE_LIB: load another build of the oracle (the tests that plant a
+# mistake in a copy of the C file and check that the pins catch it)
+LIB = os.environ.get("REWL_ORACLE_LIB") or os.path.join(HERE, "librewl_oracle.so")
 
 MODELS = {"ising": 0, "potts": 1, "ea": 2, "ea3": 3}
 
