@@ -13,26 +13,50 @@ from conftest import ROOT
 SRC = os.path.join(ROOT, "oracle", "rewl_oracle.c")
 
 # the fast pins that check the walk, the schedule, the exchange and energies
-PINS = ("sweep_samples_inverse_dos or exchange_keeps_detailed_balance or merge_and_schedule "
+WALK = ("sweep_samples_inverse_dos or exchange_keeps_detailed_balance or merge_and_schedule "
         "or walker_energy_tracks_spins or small_models_converge_to_brute_force")
 
+# planted mistake: (text in the oracle, replacement, pins expected to catch it)
 MUTATIONS = {
     "acceptance difference with its operands swapped": (
         "double d = lng[bin_of(run, E) - lo] - lng[bin_of(run, En) - lo];",
-        "double d = lng[bin_of(run, En) - lo] - lng[bin_of(run, E) - lo];"),
+        "double d = lng[bin_of(run, En) - lo] - lng[bin_of(run, E) - lo];", WALK),
     "acceptance test reversed": (
         "if (orc_ln_u(u) < d) {",
-        "if (orc_ln_u(u) > d) {"),
+        "if (orc_ln_u(u) > d) {", WALK),
     "ln f quartered instead of halved": (
         "run->lnf[k] = run->lnf[k] * 0.5;",
-        "run->lnf[k] = run->lnf[k] * 0.25;"),
+        "run->lnf[k] = run->lnf[k] * 0.25;", WALK),
     "a wrong neighbour in the Ising energy change": (
         "return 2 * (int64_t)s[i] * (s[rt] + s[lf] + s[dn] + s[up]);",
-        "return 2 * (int64_t)s[i] * (s[rt] + s[rt] + s[dn] + s[up]);"),
+        "return 2 * (int64_t)s[i] * (s[rt] + s[rt] + s[dn] + s[up]);", WALK),
     "the second term of Eq. (1) with its sign flipped": (
         "(gj[bin_of(run, EY) - lj] - gj[bin_of(run, EX) - lj]);",
-        "(gj[bin_of(run, EX) - lj] - gj[bin_of(run, EY) - lj]);"),
+        "(gj[bin_of(run, EX) - lj] - gj[bin_of(run, EY) - lj]);", WALK),
+    "the merge summing ln g instead of averaging": (
+        "double mean = pow2 ? sum * inv : sum / (double)m;",
+        "double mean = sum;", WALK),
+    "flatness without the threshold p": (
+        "return (double)hmin * (double)n >= run->p * (double)sum;",
+        "return (double)hmin * (double)n >= (double)sum;", WALK),
+    "a Philox round multiplier off by two": (
+        "uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;",
+        "uint64_t p0 = (uint64_t)0xD2511F55u * (uint64_t)c0;", "philox_matches_rocrand"),
+    "the ln u series shifted by one term": (
+        "Q = Q * z + 1.0 / (double)(2 * i + 1);",
+        "Q = Q * z + 1.0 / (double)(2 * i + 3);", "ln_u_accuracy"),
+    "the joining point one bin late": (
+        "if (diff < best_diff) { best_diff = diff; best = prev; }",
+        "if (diff < best_diff) { best_diff = diff; best = b; }",
+        "stitch_picks_matching_slope or stitch_recovers_exact_pieces"),
+    "windows rounded the wrong way": (
+        "lo[k] = (int64_t)floor(x);",
+        "lo[k] = (int64_t)ceil(x);", "partition_examples"),
+    "the 1/t rule never switched on": (
+        "if (run->schedule == 1 && run->lnf[k] < Wt) {",
+        "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),
 }
+PINS = " or ".join(sorted({m[2] for m in MUTATIONS.values()}))
 
 
 def _build(tmp_path, name, text):
@@ -45,23 +69,23 @@ def _build(tmp_path, name, text):
     return lib
 
 
-def _pins_pass(lib):
+def _pins_pass(lib, pins):
     env = dict(os.environ, REWL_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", PINS],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", pins],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return r.returncode == 0, r.stdout[-2000:]
 
 
 def test_unmodified_copy_passes(tmp_path):
-    ok, out = _pins_pass(_build(tmp_path, "clean", open(SRC).read()))
+    ok, out = _pins_pass(_build(tmp_path, "clean", open(SRC).read()), PINS)
     assert ok, out
 
 
 @pytest.mark.parametrize("what", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(tmp_path, what):
-    old, new = MUTATIONS[what]
+    old, new, pins = MUTATIONS[what]
     text = open(SRC).read()
     assert text.count(old) == 1, what
-    ok, out = _pins_pass(_build(tmp_path, "mutant", text.replace(old, new)))
+    ok, out = _pins_pass(_build(tmp_path, "mutant", text.replace(old, new)), pins)
     assert not ok, f"the pins did not catch: {what}"
