@@ -52,6 +52,16 @@ MUTATIONS = {
     "windows rounded the wrong way": (
         "lo[k] = (int64_t)floor(x);",
         "lo[k] = (int64_t)ceil(x);", "partition_examples"),
+    "the +-J energy change using the site's own coupling to the left": (
+        "(J[2 * i] * s[rt] + J[2 * lf] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * up + 1] * s[up]);",
+        "(J[2 * i] * s[rt] + J[2 * i] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * up + 1] * s[up]);",
+        WALK),
+    "the Potts energy change with its sign flipped": (
+        "return (int64_t)same_old - same_new;",
+        "return (int64_t)same_new - same_old;", WALK),
+    "the 3D glass taking the coupling of the wrong site backwards": (
+        "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * dn + a] * s[dn];",
+        "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * i + a] * s[dn];", WALK),
     "the 1/t rule never switched on": (
         "if (run->schedule == 1 && run->lnf[k] < Wt) {",
         "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),
