@@ -62,6 +62,12 @@ MUTATIONS = {
     "the 3D glass taking the coupling of the wrong site backwards": (
         "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * dn + a] * s[dn];",
         "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * i + a] * s[dn];", WALK),
+    "the ground state normalised to ln(q + 1)": (
+        "target = log(run->model == ORC_POTTS ? (double)run->q : 2.0);",
+        "target = log((double)run->q + 1.0);", "small_models_converge_to_brute_force"),
+    "the glass normalisation missing the log of its sum": (
+        "ref = mx + log(sum);",
+        "ref = mx;", "small_models_converge_to_brute_force"),
     "the 1/t rule never switched on": (
         "if (run->schedule == 1 && run->lnf[k] < Wt) {",
         "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),
