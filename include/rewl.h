@@ -149,14 +149,14 @@ int rewl_step(rewl_ctx *h, int64_t rounds);
 /* Stitched, normalised ln g over all n_bins = (e_max - e_min)/e_step + 1
  * energy bins; bins no walker visited hold -INFINITY.  Normalisation: Ising
  * ln g(-2N) = ln 2, Potts ln g(-2N) = ln q when the requested range started at
- * -2N; EA: ln sum g = N ln 2 when it was the whole [-2N, 2N]; otherwise the
- * lowest visited bin is 0.  cap: entries available in out.  Returns
+ * -2N; EA and EA3: ln sum g = N ln 2 when it was the whole [-2N, 2N]
+ * (resp. [-3N, 3N]); otherwise the lowest visited bin is 0.  cap: entries available in out.  Returns
  * REWL_NOT_CONVERGED (with the data) when some window is not done yet. */
 int rewl_get_lng(rewl_ctx *h, double *out, int64_t cap, int64_t *n_bins, int64_t *e_min,
                  int64_t *e_step);
 
-/* Raw state of walker w = window * walkers_per_window + slot: spins (L*L int8,
- * Potts states 0..q-1), energy, attempts made, flat flag, and the window-local
+/* Raw state of walker w = window * walkers_per_window + slot: spins (n_sites
+ * int8, L*L, or L^3 for EA3; Potts states 0..q-1), energy, attempts made, flat flag, and the window-local
  * ln g / H / visited arrays (hi - lo + 1 entries of the walker's window).  Any
  * output pointer may be NULL. */
 int rewl_get_walker(rewl_ctx *h, int w, int8_t *spins, int64_t *E, uint64_t *t, int *flat,
