@@ -174,11 +174,6 @@ int rewl_get_info(rewl_ctx *h, int64_t *n_bins, int64_t *e_min, int64_t *e_step,
                   int *n_windows, int *walkers_per_window, int *n_sites, int64_t *rounds,
                   uint64_t *attempts, uint64_t *accepts, uint64_t *ex_prop, uint64_t *ex_acc);
 
-/* Timing of the sweep kernel: with on != 0, every later round records a HIP
- * event right before and right after its sweep launch on the run's stream;
- * rewl_get_timing synchronises the stream and returns the summed elapsed time
- * of those launches (milliseconds) and their number since the last
- * rewl_set_timing.  Costs two event records per round; off by default. */
 /* Round in which each window first merged (halved ln f), -1 where it has not
  * yet: out[k] for k < min(cap, n_windows).  With a run on the equal partition
  * stepped until every entry is >= 0, these are the first-iteration times that
@@ -228,6 +223,11 @@ int rewl_save(rewl_ctx *h, const char *path);
 int rewl_load(rewl_ctx **out, const char *path, void *device_buffer, size_t buffer_bytes,
               void *hip_stream);
 
+/* Timing of the sweep kernel: with on != 0, every later round records a HIP
+ * event right before and right after its sweep launch on the run's stream;
+ * rewl_get_timing synchronises the stream and returns the summed elapsed time
+ * of those launches (milliseconds) and their number since the last
+ * rewl_set_timing.  Costs two event records per round; off by default. */
 int rewl_set_timing(rewl_ctx *h, int on);
 int rewl_get_timing(rewl_ctx *h, double *sweep_ms, int64_t *sweep_launches);
 
@@ -246,6 +246,8 @@ void rewl_destroy(rewl_ctx *h);
  * returns (owned by the batch).
  *  walkers_per_wave: 1, 2, 4 or 8 (0: 1); more walkers per wave share each
  *    wave's instructions, fewer give each walker a whole wave (lower latency).
+ *    (The sweep's instantiation also depends on whether a launch has more
+ *    waves than the device has compute units; results never do.)
  *  REWL_EINVAL if the walkers of one wave do not fit the LDS of a CU. */
 typedef struct rewl_batch rewl_batch;
 int rewl_batch_create(rewl_batch **out, const rewl_params *runs, int n_runs,
