@@ -211,3 +211,25 @@ def test_no_cpu_fallback_without_a_gpu(rewl):
         rewl.Batch([kw], walkers_per_wave=1)
     with pytest.raises(RuntimeError, match="no GPU"):
         rewl.Server(device_budget_bytes=1 << 20)
+
+
+def test_plain_c_program_uses_the_library(tmp_path):
+    """A C11 program (tests/c_abi_probe.c) compiles against include/rewl.h with
+    gcc, links librewl.so and runs the host-only entry points without a GPU."""
+    import subprocess
+
+    import paper_1305_5615_amd as rewl
+
+    if not os.path.exists(rewl.LIB):
+        from paper_1305_5615_amd import build
+
+        build.build()
+    exe = tmp_path / "probe"
+    libdir = os.path.dirname(rewl.LIB)
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror",
+                    "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_probe.c"), "-o", str(exe),
+                    "-L", libdir, "-lrewl", "-Wl,-rpath," + libdir, "-lm"], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "c-abi probe: ok" in r.stdout
