@@ -233,3 +233,20 @@ def test_plain_c_program_uses_the_library(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "c-abi probe: ok" in r.stdout
+
+
+def test_missing_library_fails_loudly():
+    """Without librewl.so the binding raises at the first call: nothing falls
+    back to another implementation."""
+    import subprocess
+    import sys
+
+    code = ("import paper_1305_5615_amd as r\n"
+            "r.LIB = '/nonexistent/librewl.so'\n"
+            "try:\n"
+            "    r.footprint(model='ising', L=8)\n"
+            "except ImportError as e:\n"
+            "    print('refused:', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0 and "refused:" in out.stdout, out.stdout + out.stderr
