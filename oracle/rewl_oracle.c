@@ -317,6 +317,8 @@ struct orc_run {
     uint8_t *vis;       /* nw * Wmax */
     uint64_t *n_acc;    /* nw */
     uint64_t ex_prop, ex_acc;
+    int *perm;          /* m: exchange partner permutation (scratch) */
+    int8_t *swap;       /* N: configuration swap buffer (scratch) */
 };
 
 static int window_of(const orc_run *run, int w) { return w / run->m; }
@@ -335,6 +337,7 @@ void orc_destroy(orc_run *run)
     free(run->J); free(run->lo); free(run->hi); free(run->lnf); free(run->done); free(run->phase);
     free(run->finish); free(run->first); free(run->spins); free(run->E); free(run->t); free(run->flat);
     free(run->lng); free(run->H); free(run->vis); free(run->n_acc);
+    free(run->perm); free(run->swap);
     free(run);
 }
 
@@ -457,9 +460,11 @@ int orc_create(orc_run **out, int model, int L, int q, const int8_t *couplings,
     run->H = calloc(nw * run->Wmax, sizeof(uint32_t));
     run->vis = calloc(nw * run->Wmax, 1);
     run->n_acc = calloc(nw, sizeof(uint64_t));
+    run->perm = calloc((size_t)m, sizeof(int));
+    run->swap = calloc((size_t)N, 1);
     if (!run->J || !run->lnf || !run->done || !run->phase || !run->finish || !run->first ||
-        !run->spins || !run->E ||
-        !run->t || !run->flat || !run->lng || !run->H || !run->vis || !run->n_acc) {
+        !run->spins || !run->E || !run->t || !run->flat || !run->lng || !run->H ||
+        !run->vis || !run->n_acc || !run->perm || !run->swap) {
         orc_destroy(run);
         return -2;
     }
@@ -602,8 +607,8 @@ static uint32_t next_word(word_src *ws)
 static void exchange(orc_run *run, int64_t round)
 {
     int m = run->m, N = run->N;
-    int *perm = malloc(sizeof(int) * (size_t)m);
-    int8_t *tmp = malloc((size_t)N);
+    int *perm = run->perm;
+    int8_t *tmp = run->swap;
     for (int k = (int)(round % 2); k + 1 < run->h; k += 2) {
         if (run->done[k] || run->done[k + 1]) continue;
         word_src ws = {run->seed, (uint64_t)round, (uint32_t)k, 0, 4, {0, 0, 0, 0}};
@@ -635,8 +640,6 @@ static void exchange(orc_run *run, int64_t round)
             }
         }
     }
-    free(perm);
-    free(tmp);
 }
 
 static int all_done(const orc_run *run)
@@ -798,6 +801,7 @@ int orc_get_lng(orc_run *run, double *out, int64_t cap)
     int h = run->h;
     double *P = malloc(sizeof(double) * (size_t)h * run->Wmax);
     uint8_t *V = malloc((size_t)h * run->Wmax);
+    if (!P || !V) { free(P); free(V); return -2; }
     for (int k = 0; k < h; ++k) {
         int w = k * run->m; /* all walkers of a window agree after the last merge */
         memcpy(P + (size_t)k * run->Wmax, run->lng + (size_t)w * run->Wmax,
