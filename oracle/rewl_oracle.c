@@ -44,6 +44,13 @@
  *  - randomness: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), key = seed,
  *    counters (t, walker, stream); the acceptance test u < P is taken as
  *    ln u < ln P with ln u from the series ln x = 2 atanh((x-1)/(x+1)).
+ *
+ * Pins: every function here is checked by the CPU tests against something other
+ * than itself (exact densities of states, enumeration, invariants, rocRAND's
+ * Philox, a high-precision logarithm, sampled distributions).  Parity
+ * unpinned: the accuracy of the large workloads (q = 10 Potts 64x64, +-J 24x24,
+ * the 12^3 glass) has no exact density of states to compare with; there only
+ * the invariants of the small cases and bit-exactness of the GPU path apply.
  */
 #include "rewl_oracle.h"
 
