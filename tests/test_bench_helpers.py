@@ -1,0 +1,48 @@
+"""Host-side helpers of bench.py that its reported figures rest on (no GPU)."""
+import numpy as np
+
+from conftest import load_ising_golden
+
+
+def test_exact_error_measures_the_largest_deviation():
+    import bench
+    from workloads import run_params
+
+    p = run_params("ising32", seed=1)
+    _, ref = load_ising_golden(32)
+    assert bench.exact_error(p, ref) == 0.0
+    off = ref.copy()
+    b = int(np.flatnonzero(np.isfinite(ref))[100])
+    off[b] += 0.015
+    assert abs(bench.exact_error(p, off) - 0.015) < 1e-12
+    # a visited set different from the exact support is an infinite error
+    bad = ref.copy()
+    bad[b] = -np.inf
+    assert bench.exact_error(p, bad) == float("inf")
+    # no stored exact DOS for other models
+    assert bench.exact_error(run_params("potts64", seed=1), ref) is None
+
+
+def test_percentile_and_roofline_constants():
+    import bench
+
+    assert bench.percentile([], 50) is None
+    assert bench.percentile([1.0, 2.0, 3.0], 50) == 2.0
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in T lane-slots/s
+    assert abs(bench.VALU_PEAK_TOPS - 256 * 4 * 16 * 2.4e9 / 1e12) < 1e-9
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    """The HBM traffic the benchmark reports comes from profiles/ only while
+    they were taken on the current device sources (a kernel change without new
+    profiles leaves it null, which this test reports as a skip)."""
+    import os
+
+    import pytest
+
+    import bench
+
+    for tag in ("ising32", "ea24x256_P8"):
+        assert os.path.exists(os.path.join(bench.ROOT, "profiles", f"sweep_{tag}.md")), tag
+        if bench.profiled_traffic(tag) is None:
+            pytest.skip(f"profiles/sweep_{tag}.md was taken on other kernel sources")
