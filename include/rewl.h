@@ -216,7 +216,10 @@ int rewl_jackknife(const double *lng, int runs, int64_t n_bins, double *mean, do
  * rewl_load recreates the run from such a file -- device memory as in
  * rewl_create_ex -- so that stepping it continues exactly as the saved run
  * would have (same rounds, same results, bit for bit).  REWL_ECORRUPT: not a
- * checkpoint, truncated, or checksum (FNV-1a 64 over the file) mismatch;
+ * checkpoint, truncated, checksum (FNV-1a 64 over the file) mismatch, or a
+ * saved state that does not fit the saved parameters (windows, every walker's
+ * energy inside its window, spins that are states of the model, +-1
+ * couplings), checked on the host before anything reaches the GPU;
  * REWL_EINVAL: the file cannot be opened or written.  Works for a run of a
  * batch too (it is saved alone and loads as a run of its own). */
 int rewl_save(rewl_ctx *h, const char *path);

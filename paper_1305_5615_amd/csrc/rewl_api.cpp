@@ -857,7 +857,7 @@ struct Reader {
     }
     const char *bytes(size_t n)
     {
-        if (at + n > s.size()) {
+        if (n > s.size() - at) {
             ok = false;
             return nullptr;
         }
@@ -868,6 +868,46 @@ struct Reader {
 };
 
 const char kMagic[8] = {'R', 'E', 'W', 'L', 'S', 'A', 'V', '1'};
+
+// The saved state goes to kernels that index LDS with the walkers' energies and
+// windows and combine spins and couplings into energy changes: a file whose
+// state does not fit its own parameters is refused (the checksum guards against
+// accidents, not against a made-up file).
+int check_saved_state(const rewl_params &p, const Geometry &g, const char *slab, size_t ns)
+{
+    const Layout l = layout(&p, g);
+    if (ns != l.total) return fail(REWL_ECORRUPT, "saved state has the wrong size");
+    for (int k = 0; k < p.n_windows; ++k) {
+        int32_t lo, hi;
+        std::memcpy(&lo, slab + l.lo + 4 * (size_t)k, 4);
+        std::memcpy(&hi, slab + l.hi + 4 * (size_t)k, 4);
+        if (lo != g.lo[k] || hi != g.hi[k])
+            return fail(REWL_ECORRUPT, "saved windows disagree with the parameters");
+    }
+    for (int w = 0; w < g.nw; ++w) {
+        int32_t e;
+        std::memcpy(&e, slab + l.E + 4 * (size_t)w, 4);
+        const int k = w / p.walkers_per_window;
+        const int64_t elo = g.e_min + g.lo[k] * g.step, ehi = g.e_min + g.hi[k] * g.step;
+        if (e < elo || e > ehi || (e - g.e_min) % g.step != 0)
+            return fail(REWL_ECORRUPT, "a saved energy lies outside its walker's window");
+        const int8_t *sp = reinterpret_cast<const int8_t *>(slab + l.spins + (size_t)w * g.Npad);
+        for (int i = 0; i < g.N; ++i) {
+            const int v = sp[i];
+            if (p.model == REWL_POTTS ? (v < 0 || v >= p.q) : (v != 1 && v != -1))
+                return fail(REWL_ECORRUPT, "a saved spin is not a state of the model");
+        }
+    }
+    // coupling words: EA four +-1 bytes per site; EA3 six, then two zero bytes
+    const int jw = model_j_words(p.model);
+    for (size_t i = 0; i < (size_t)jw * 4 * (size_t)g.N; ++i) {
+        const int8_t j = (int8_t)slab[l.J4 + i];
+        const bool pad = jw == 2 && i % 8 >= 6;
+        if (pad ? j != 0 : (j != 1 && j != -1))
+            return fail(REWL_ECORRUPT, "a saved coupling is not +-1");
+    }
+    return REWL_OK;
+}
 
 }  // namespace
 }  // extern "C++"
@@ -963,6 +1003,19 @@ int rewl_load(rewl_ctx **out, const char *path, void *device_buffer, size_t buff
     p.couplings = couplings.empty() ? nullptr : couplings.data();
     p.window_lo = lo.data();
     p.window_hi = hi.data();
+    const bool glass = p.model == REWL_EA || p.model == REWL_EA3;
+    if (glass ? (p.L < 2 || p.L > 256) : nc != 0)
+        return fail(REWL_ECORRUPT, "checkpoint couplings do not fit the model");
+    if (glass) {
+        const uint64_t n = (uint64_t)p.L * (uint64_t)p.L * (p.model == REWL_EA3 ? (uint64_t)p.L : 1u);
+        if (nc != n * (uint64_t)bonds_per_site(p.model))
+            return fail(REWL_ECORRUPT, "checkpoint couplings do not fit the model");
+    }
+    Geometry g;
+    int vrc = validate(&p, g);
+    if (vrc) return vrc;
+    vrc = check_saved_state(p, g, slab, (size_t)ns);
+    if (vrc) return vrc;
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     rewl_ctx *h = nullptr;
     int rc = make_run(&h, &p, device_buffer, buffer_bytes, stream, slab, (size_t)ns);

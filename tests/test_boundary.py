@@ -250,3 +250,50 @@ def test_missing_library_fails_loudly():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
                          timeout=120)
     assert out.returncode == 0 and "refused:" in out.stdout, out.stdout + out.stderr
+
+
+def _fnv1a(data):
+    h = 1469598103934665603
+    for b in data:
+        h ^= b
+        h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _checkpoint_bytes(model, L, q, h, m, lo, hi, couplings, slab, nc=None):
+    """A file in the checkpoint format (the fields rewl_save writes, in order)
+    with a valid checksum."""
+    import struct
+
+    s = b"REWLSAV1" + struct.pack("<6i", model, L, q, h, m, 0)
+    N = L * L
+    s += struct.pack("<2q4dqQ", -2 * N, 2 * N if model != 1 else 0, 0.75, 0.8, 1.0, 1e-3,
+                     1000, 1)
+    s += struct.pack("<Q", len(couplings) if nc is None else nc) + bytes(couplings)
+    s += struct.pack(f"<{h}q", *lo) + struct.pack(f"<{h}q", *hi)
+    s += struct.pack("<Q", len(slab)) + slab
+    return s + struct.pack("<Q", _fnv1a(s))
+
+
+def test_load_refuses_a_made_up_state(tmp_path, rewl, oracle_lib):
+    """A file with a valid checksum whose device state does not fit its own
+    parameters (windows, energies, spins, couplings), or whose lengths are
+    absurd, is refused on the host with REWL_ECORRUPT before any GPU work."""
+    import ctypes as C
+
+    lo, hi = oracle_lib.partition(65, 4, 0.75)              # 8x8 Ising, 4 windows
+    dev, _ = rewl.footprint(model="ising", L=8, n_windows=4, walkers_per_window=2)
+    h = C.c_void_p()
+    f = tmp_path / "made_up.rewl"
+    # garbage state of the right size
+    f.write_bytes(_checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"", b"\x7f" * dev))
+    assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
+    assert b"window" in rewl.lib().rewl_last_error()
+    # a state of the wrong size
+    f.write_bytes(_checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"", bytes(dev - 256)))
+    assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
+    # couplings claimed for a model without them, and an absurd couplings length
+    f.write_bytes(_checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"\x01" * 128, bytes(dev)))
+    assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
+    f.write_bytes(_checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"", bytes(dev), nc=(1 << 63)))
+    assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
