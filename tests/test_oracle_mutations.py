@@ -68,6 +68,24 @@ MUTATIONS = {
     "the glass normalisation missing the log of its sum": (
         "ref = mx + log(sum);",
         "ref = mx;", "small_models_converge_to_brute_force"),
+    "an accepted move not updating the walker's energy": (
+        "E = En;\n                acc += 1;",
+        "acc += 1;", WALK),
+    "exchanges always starting from the lowest window pair": (
+        "for (int k = (int)(round % 2); k + 1 < run->h; k += 2) {",
+        "for (int k = 0; k + 1 < run->h; k += 2) {", "exchange_pairs_alternate"),
+    "exchanges proposed between every neighbouring pair each round": (
+        "for (int k = (int)(round % 2); k + 1 < run->h; k += 2) {",
+        "for (int k = 0; k + 1 < run->h; k += 1) {", "exchange_pairs_alternate"),
+    "a merge leaving the walkers' flatness flags set": (
+        "for (int s = 0; s < m; ++s) run->flat[k * m + s] = 0;",
+        "", "merge_and_schedule"),
+    "flatness counting bins the walker never visited": (
+        "if (!vis[b]) continue;",
+        "", "merge_and_schedule"),
+    "balanced windows sized as if they did not overlap": (
+        "double w = F[B - 1] / (1.0 + (double)(h - 1) * (1.0 - o));",
+        "double w = F[B - 1] / (double)h;", "balanced_partition_uniform_is_equal"),
     "the 1/t rule never switched on": (
         "if (run->schedule == 1 && run->lnf[k] < Wt) {",
         "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),

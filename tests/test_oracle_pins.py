@@ -464,12 +464,58 @@ def test_exchange_keeps_detailed_balance(oracle_lib):
         assert rel.max() < 0.25, (w, rel.max())
 
 
+def test_exchange_pairs_alternate(oracle_lib):
+    """Exchanges run between neighbouring windows, the pairs (k, k+1) with
+    k = round mod 2, one proposal per walker of the lower window: with 4 windows
+    of 3 walkers that is 2 pairs (6 proposals) in even rounds and 1 pair
+    (3 proposals) in odd ones."""
+    run = oracle_lib.Run("ising", 6, n_windows=4, walkers_per_window=3, S=200, seed=9,
+                         lnf_final=1e-12)
+    prev = run.stats()["ex_prop"]
+    for r in range(12):
+        run.step(1)
+        assert not any(w["done"] for w in run.windows())
+        now = run.stats()["ex_prop"]
+        assert now - prev == (6 if r % 2 == 0 else 3), (r, now - prev)
+        prev = now
+
+
+@pytest.mark.parametrize("model,q,L", [("ising", 2, 6), ("potts", 3, 5), ("ea", 2, 6)])
+def test_walkers_stay_in_their_windows(oracle_lib, model, q, L):
+    """A move or an exchange that would take a walker out of its window is
+    rejected, so every walker's energy stays in its window through rounds of
+    sweeps and exchanges (Eq. (1) is applied only when both energies lie in both
+    windows); exchanges do get accepted."""
+    from workloads import ea_couplings
+
+    J = ea_couplings(L, 5) if model == "ea" else None
+    run = oracle_lib.Run(model, L, q=q, couplings=J, n_windows=4, walkers_per_window=2,
+                         overlap=0.5, S=300, seed=11, lnf_final=1e-12)
+    for _ in range(40):
+        run.step(1)
+        for w in range(run.h * run.m):
+            win = run.window(w // run.m)
+            E = run.walker(w)["E"]
+            assert (E - run.e_min) % run.e_step == 0
+            assert win["lo"] <= (E - run.e_min) // run.e_step <= win["hi"], (w, E, win)
+    assert run.stats()["ex_acc"] > 0
+
+
 # -------------------------------------------------------------- schedule --
+def _flat_by_definition(st, p):
+    """The flatness criterion written out: over the visited bins of the window,
+    the smallest histogram entry is at least p times the mean entry (compared as
+    min * n >= p * sum, free of the division's rounding)."""
+    h = st["H"][st["visited"] > 0].astype(np.float64)
+    return bool(h.size > 0 and h.min() * h.size >= p * h.sum())
+
+
 def test_merge_and_schedule(oracle_lib):
     """Windows merge only when all m walkers are flat; ln f halves; H resets."""
     run = oracle_lib.Run("ising", 6, n_windows=2, walkers_per_window=2, S=2000, seed=4,
                          lnf_final=1e-3)
     prev = [1.0, 1.0]
+    was_flat = [False] * 4
     for _ in range(400):
         run.step(1)
         for k in range(2):
@@ -482,7 +528,20 @@ def test_merge_and_schedule(oracle_lib):
                 if not win["done"]:
                     # fresh iteration: only the exchange step ran after the merge
                     assert all(s["H"].sum() == 0 for s in sts)
+                    assert not any(s["flat"] for s in sts)
                 prev[k] = win["lnf"]
+            elif not win["done"]:
+                # no merge: a walker's flag is the flatness of its histogram over
+                # the bins it visited (min H >= p * mean H, p = 0.8) the first
+                # time that holds, and stays set until the window merges
+                for s, st in enumerate(sts):
+                    w = 2 * k + s
+                    if not was_flat[w]:
+                        assert st["flat"] == _flat_by_definition(st, 0.8), (w, st["H"])
+                    else:
+                        assert st["flat"]
+            for s, st in enumerate(sts):
+                was_flat[2 * k + s] = st["flat"]
             assert np.array_equal(sts[0]["visited"] > 0, sts[0]["lng"] > 0)
         if run.info()["done"]:
             break
