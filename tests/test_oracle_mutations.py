@@ -86,6 +86,12 @@ MUTATIONS = {
     "balanced windows sized as if they did not overlap": (
         "double w = F[B - 1] / (1.0 + (double)(h - 1) * (1.0 - o));",
         "double w = F[B - 1] / (double)h;", "balanced_partition_uniform_is_equal"),
+    "the 1/t increment taken with t counted before the attempt": (
+        "if (one_over_t) lnf = Wd / (double)run->t[w];",
+        "if (one_over_t) lnf = Wd / (double)(run->t[w] - 1);", "one_over_t_increments"),
+    "the 1/t increment taken as W/(t+1)": (
+        "if (one_over_t) lnf = Wd / (double)run->t[w];",
+        "if (one_over_t) lnf = Wd / (double)(run->t[w] + 1);", "one_over_t_increments"),
     "the 1/t rule never switched on": (
         "if (run->schedule == 1 && run->lnf[k] < Wt) {",
         "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),

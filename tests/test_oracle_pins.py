@@ -593,6 +593,37 @@ def test_one_over_t_schedule(oracle_lib):
     assert all(x is not None for x in switched), switched
 
 
+def test_one_over_t_increments(oracle_lib):
+    """In the 1/t phase the j-th attempt of a walker (j counted after the
+    attempt) adds W/j to ln g of the bin it ends in, so one round of S attempts
+    raises the sum of a walker's ln g over the window by the sum of W/j for
+    j = t0+1 .. t0+S; the end-of-round average over the window's walkers, which
+    all share t, and the exchange step (no ln g update) keep that sum."""
+    S = 3000
+    run = oracle_lib.Run("ising", 6, n_windows=2, walkers_per_window=2, S=S, seed=7,
+                         lnf_final=1e-9, schedule="1/t")
+    checked = 0
+    prev = [None, None]   # (t, sum of ln g) once the window runs the 1/t rule
+    for _ in range(4000):
+        run.step(1)
+        for k in range(2):
+            win = run.window(k)
+            W = win["hi"] - win["lo"] + 1
+            st = run.walker(2 * k)
+            total = math.fsum(st["lng"])
+            if prev[k] is not None and not prev[k][2]:
+                t0, before, _ = prev[k]
+                assert st["t"] == t0 + S
+                want = math.fsum(W / j for j in range(t0 + 1, t0 + S + 1))
+                assert abs((total - before) - want) < 1e-8, (k, total - before, want)
+                checked += 1
+            if win["lnf"] == W / st["t"]:   # in the 1/t phase (set at this merge)
+                prev[k] = (st["t"], total, win["done"])
+        if checked >= 20 or run.info()["done"]:
+            break
+    assert checked >= 20, checked
+
+
 def test_one_over_t_removes_saturation(oracle_lib):
     """6x6 Ising against the exact DOS: halving to ln f = 1e-6 stalls at errors
     of 0.1-0.2, the 1/t rule reaches a few hundredths by ln f = 1e-5."""
