@@ -220,7 +220,8 @@ int rewl_jackknife(const double *lng, int runs, int64_t n_bins, double *mean, do
  * saved state that does not fit the saved parameters (windows, every walker's
  * energy inside its window, spins that are states of the model, +-1
  * couplings), checked on the host before anything reaches the GPU;
- * REWL_EINVAL: the file cannot be opened or written.  Works for a run of a
+ * REWL_EINVAL: the file cannot be opened or written, or the parameters it
+ * holds are ones rewl_create_ex refuses.  Works for a run of a
  * batch too (it is saved alone and loads as a run of its own). */
 int rewl_save(rewl_ctx *h, const char *path);
 int rewl_load(rewl_ctx **out, const char *path, void *device_buffer, size_t buffer_bytes,

@@ -297,3 +297,36 @@ def test_load_refuses_a_made_up_state(tmp_path, rewl, oracle_lib):
     assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
     f.write_bytes(_checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"", bytes(dev), nc=(1 << 63)))
     assert rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None) == -5
+
+
+def test_load_survives_corrupted_fields(tmp_path, rewl, oracle_lib):
+    """Checkpoints with random bytes changed, fields set to extreme values or the
+    body cut short, each with its checksum recomputed so the reader gets past it,
+    are all refused on the host (REWL_ECORRUPT, or REWL_EINVAL for parameters
+    that are not a valid run) with a message, and never crash the reader."""
+    lo, hi = oracle_lib.partition(65, 4, 0.75)              # 8x8 Ising, 4 windows
+    dev, _ = rewl.footprint(model="ising", L=8, n_windows=4, walkers_per_window=2)
+    base = _checkpoint_bytes(0, 8, 2, 4, 2, lo, hi, b"", b"\x7f" * dev)[:-8]
+    rng = np.random.default_rng(21)
+    extremes = [0, 2 ** 64 - 1, 2 ** 63, 2 ** 63 - 1, 2 ** 31 - 1, 2 ** 31]
+    f = tmp_path / "fuzzed.rewl"
+    h = C.c_void_p()
+    seen = set()
+    for it in range(400):
+        body = bytearray(base)
+        kind = it % 3
+        if kind == 0:                      # change 1-4 bytes of the parameters and windows
+            for _ in range(int(rng.integers(1, 5))):
+                body[int(rng.integers(8, 200))] ^= int(rng.integers(1, 256))
+        elif kind == 1:                    # an 8-byte field set to an extreme value
+            at = int(rng.integers(8, 190))
+            body[at:at + 8] = int(extremes[it % len(extremes)]).to_bytes(8, "little")
+        else:                              # the body cut short
+            body = body[:int(rng.integers(8, len(body)))]
+        f.write_bytes(bytes(body) + int(_fnv1a(body)).to_bytes(8, "little"))
+        rc = rewl.lib().rewl_load(C.byref(h), str(f).encode(), None, 0, None)
+        assert rc in (-1, -5), (it, rc)
+        assert h.value is None
+        assert rewl.lib().rewl_last_error()
+        seen.add(rc)
+    assert seen == {-1, -5}
