@@ -46,3 +46,22 @@ def test_committed_profiles_match_the_kernel_sources():
         assert os.path.exists(os.path.join(bench.ROOT, "profiles", f"sweep_{tag}.md")), tag
         if bench.profiled_traffic(tag) is None:
             pytest.skip(f"profiles/sweep_{tag}.md was taken on other kernel sources")
+
+
+def test_more_than_one_gpu_is_refused_before_any_gpu_work():
+    """bench.py measures one GPU: --gpus N with N > 1 (or a multi-rank launch)
+    exits with status 2 and a message saying so, before it imports torch."""
+    import os
+    import subprocess
+    import sys
+
+    from conftest import ROOT
+
+    for argv, env in ((["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv],
+                           env=dict(os.environ, **env), capture_output=True, text=True,
+                           timeout=120, cwd=ROOT)
+        assert r.returncode == 2, (argv, env, r.stderr)
+        assert "exactly one GPU" in r.stderr and "--gpus 1" in r.stderr
+        assert r.stdout == ""
+
