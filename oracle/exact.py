@@ -9,6 +9,8 @@ These are the truth sources the oracle is pinned against (the paper compares its
 * ``ising_dos_transfer``: the 2D Ising DOS on an L x L torus by a row-to-row
   transfer matrix over polynomials in the number of unsatisfied bonds, in exact
   integer arithmetic (independent of the closed form below).
+* ``potts_dos_transfer``: the 2D q-state Potts DOS on an L x L torus by a row
+  transfer matrix (exact while q^N < 2^53: 5 x 5 at q = 3, 4 x 4 at q = 4).
 * ``ising_dos_exact``: the 2D Ising DOS on an L x L torus (L even) from
   Kaufman's closed-form partition function of the finite torus (B. Kaufman,
   Phys. Rev. 76, 1232 (1949)), turned into the integer coefficients g(E) the way
@@ -129,6 +131,46 @@ def ising_dos_transfer(L):
     for j in range(N + 1):
         out.append(total[2 * j])
     assert all(total[u] == 0 for u in range(1, D, 2))
+    return out
+
+
+def potts_dos_transfer(L, q):
+    """Exact 2D q-state Potts DOS on the L x L torus by a row transfer matrix.
+
+    Row states are L-digit base-q integers; the weight counts the bonds whose
+    two spins are equal (u of them, E = -u).  Rows are added one by one after
+    every fixed first row, and the periodic closure with the first row is added
+    at the end.  The counts are integers below 2^53 (checked: q^N < 2^53), so
+    the float64 matrix products, whose partial sums are integers no larger than
+    the total, are exact.  Returns a dict {E: count}.
+    """
+    N = L * L
+    if q ** N >= 2 ** 53:
+        raise ValueError("counts too large for exact float64 sums")
+    R = q ** L
+    digits = np.array([[(s // q ** c) % q for c in range(L)] for s in range(R)])
+    intra = (digits == np.roll(digits, -1, axis=1)).sum(1)          # equal bonds in a row
+    inter = (digits[:, None, :] == digits[None, :, :]).sum(2)        # equal bonds between rows
+    D = 2 * N + 1                                                     # u = 0 .. 2N
+    V = np.zeros((R, D, R))                                           # [first row, u, last row]
+    V[np.arange(R), intra, np.arange(R)] = 1.0
+    for _ in range(L - 1):
+        new = np.zeros_like(V)
+        for v in range(L + 1):
+            K = (inter == v).astype(np.float64)
+            P = (V.reshape(R * D, R) @ K).reshape(R, D, R)
+            for h in np.unique(intra):
+                cols = intra == h
+                sh = v + int(h)
+                new[:, sh:, cols] += P[:, :D - sh, cols]
+        V = new
+    total = np.zeros(D)
+    for r0 in range(R):
+        for v in range(L + 1):
+            cols = inter[:, r0] == v
+            total[v:] += V[r0, :D - v, :][:, cols].sum(1)
+    out = {-u: int(n) for u, n in enumerate(total) if n}
+    assert sum(out.values()) == q ** N
     return out
 
 

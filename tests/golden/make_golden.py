@@ -4,8 +4,9 @@ Calls only oracle.exact.  2D Ising: Kaufman's finite-torus partition function,
 inverted as Beale did; one line per energy level, "E g(E)" for L <= 16 (exact
 integers) and "E ln g(E)" with 17 significant digits for larger L.  3D +-J
 glass, 3x3x3, couplings workloads.ea3_couplings(3, 1): enumeration of all 2^27
-configurations (a few minutes), "E g(E)".
-Usage: python tests/golden/make_golden.py [L ... | ea3]   (default: 8 16 32)
+configurations (a few minutes), "E g(E)".  2D q = 3 Potts, 4x4: enumeration of all
+3^16 configurations, "E g(E)".
+Usage: python tests/golden/make_golden.py [L ... | ea3 | potts]   (default: 8 16 32)
 """
 import math
 import os
@@ -51,10 +52,25 @@ def write_ea3(L=3, seed=1):
     print("wrote", path)
 
 
+def write_potts(L=4, q=3):
+    g = exact.brute_dos("potts", L, q=q)
+    assert sum(g.values()) == q ** (L * L)
+    path = os.path.join(HERE, f"potts_L{L}_q{q}.txt")
+    with open(path, "w") as f:
+        f.write(f"# exact DOS of the 2D {q}-state Potts model, {L}x{L} torus, "
+                f"E = -sum delta(s_i, s_j); written by tests/golden/make_golden.py from "
+                f"oracle.exact\n# columns: E g(E)\n")
+        for e in sorted(g):
+            f.write(f"{e} {g[e]}\n")
+    print("wrote", path)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if args == ["ea3"]:
         write_ea3()
+    elif args == ["potts"]:
+        write_potts()
     else:
         for L in [int(a) for a in args] or [8, 16, 32]:
             write(L)

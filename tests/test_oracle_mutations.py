@@ -59,6 +59,10 @@ MUTATIONS = {
     "the Potts energy change with its sign flipped": (
         "return (int64_t)same_old - same_new;",
         "return (int64_t)same_new - same_old;", WALK),
+    "the Potts energy change counting one neighbour twice for the new state": (
+        "int same_new = (s[rt] == nw) + (s[lf] == nw) + (s[dn] == nw) + (s[up] == nw);",
+        "int same_new = (s[rt] == nw) + (s[lf] == nw) + (s[dn] == nw) + (s[dn] == nw);",
+        "potts_converges_to_exact"),
     "the 3D glass taking the coupling of the wrong site backwards": (
         "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * dn + a] * s[dn];",
         "h += (int64_t)J[3 * i + a] * s[up] + (int64_t)J[3 * i + a] * s[dn];", WALK),

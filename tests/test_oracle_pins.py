@@ -353,6 +353,71 @@ def test_brute_force_potts_counts():
     assert g[-2 * N + 4] == q * N * (q - 1)
 
 
+def _potts_golden(L, q):
+    rows = [line.split() for line in open(os.path.join(ROOT, "tests", "golden",
+                                                       f"potts_L{L}_q{q}.txt"))
+            if not line.startswith("#")]
+    return {int(e): int(n) for e, n in rows}
+
+
+def test_potts_transfer_matrix_agrees_with_enumeration():
+    """Two independent exact methods for the Potts DOS agree: the row transfer
+    matrix equals enumeration (3x3 at q = 3 and 4, the stored 4x4 q = 3 table of
+    all 3^16 configurations), and at q = 2 it equals Kaufman's Ising DOS through
+    E_P = -N + E_I / 2 (4x4, 6x6)."""
+    from oracle import exact
+
+    for q in (3, 4):
+        assert exact.potts_dos_transfer(3, q) == exact.brute_dos("potts", 3, q=q)
+    assert exact.potts_dos_transfer(4, 3) == _potts_golden(4, 3)
+    for L in (4, 6):
+        N = L * L
+        ising = exact.ising_dos_exact(L)
+        want = {-N + (-2 * N + 4 * j) // 2: n for j, n in enumerate(ising) if n}
+        assert exact.potts_dos_transfer(L, 2) == want
+
+
+@pytest.mark.parametrize("L,q", [(4, 3), (5, 3), (4, 4)])
+def test_potts_low_levels_closed_form(L, q):
+    """Sum rule and the lowest levels, counted by hand on the torus: the q ordered
+    states; one site of another state breaks 4 bonds (qN(q-1) states); a
+    two-site domino breaks 6 when both sites share a new state (2N q(q-1)) and
+    7 when they differ from each other too (2N q(q-1)(q-2)); 1, 2, 3 and 5
+    broken bonds are impossible."""
+    from oracle import exact
+
+    N = L * L
+    g = _potts_golden(L, q) if (L, q) == (4, 3) else exact.potts_dos_transfer(L, q)
+    assert sum(g.values()) == q ** N
+    lo = -2 * N
+    assert g[lo] == q
+    assert all(lo + d not in g for d in (1, 2, 3, 5))
+    assert g[lo + 4] == q * N * (q - 1)
+    assert g[lo + 6] == 2 * N * q * (q - 1)
+    assert g[lo + 7] == 2 * N * q * (q - 1) * (q - 2)
+
+
+def test_potts_converges_to_exact(oracle_lib):
+    """REWL on Potts lattices beyond enumeration's reach for a test, against the
+    exact DOS: 4x4 q = 3 under halving to ln f = 1e-6 (measured 0.075, 0.061 for
+    seeds 1, 2); 5x5 q = 3 and 4x4 q = 4 under the 1/t rule to 1e-5 (measured
+    0.037-0.067 over seeds 1-3).  Every exactly reachable level is visited, and no
+    other."""
+    from oracle import exact
+
+    cases = [(4, 3, 3, "halving", 1e-6, 1, 0.2), (4, 3, 3, "halving", 1e-6, 2, 0.2),
+             (5, 3, 4, "1/t", 1e-5, 1, 0.1), (4, 4, 3, "1/t", 1e-5, 2, 0.1)]
+    for L, q, h, sched, lf, seed, tol in cases:
+        g = _potts_golden(L, q) if (L, q) == (4, 3) else exact.potts_dos_transfer(L, q)
+        run = oracle_lib.Run("potts", L, q=q, n_windows=h, walkers_per_window=2, lnf_final=lf,
+                             S=5_000, seed=seed, schedule=sched, n_threads=4)
+        assert run.run()
+        ref = np.array([math.log(g[e]) if e in g else -np.inf for e in run.energies()])
+        lng = run.lng()
+        assert np.array_equal(np.isfinite(lng), np.isfinite(ref)), (L, q, seed)
+        assert _max_err(lng, ref) < tol, (L, q, sched, seed, _max_err(lng, ref))
+
+
 def test_brute_force_ea_symmetry():
     """On an even torus g(E) = g(-E) for any +-J couplings (flip one sublattice)."""
     from oracle import exact
