@@ -360,6 +360,20 @@ def _potts_golden(L, q):
     return {int(e): int(n) for e, n in rows}
 
 
+_POTTS_EXACT = {}
+
+
+def _potts_exact(L, q):
+    """The stored enumeration for 4x4 q = 3, else the transfer matrix (cached)."""
+    if (L, q) == (4, 3):
+        return _potts_golden(4, 3)
+    if (L, q) not in _POTTS_EXACT:
+        from oracle import exact
+
+        _POTTS_EXACT[(L, q)] = exact.potts_dos_transfer(L, q)
+    return _POTTS_EXACT[(L, q)]
+
+
 def test_potts_transfer_matrix_agrees_with_enumeration():
     """Two independent exact methods for the Potts DOS agree: the row transfer
     matrix equals enumeration (3x3 at q = 3 and 4, the stored 4x4 q = 3 table of
@@ -377,23 +391,23 @@ def test_potts_transfer_matrix_agrees_with_enumeration():
         assert exact.potts_dos_transfer(L, 2) == want
 
 
-@pytest.mark.parametrize("L,q", [(4, 3), (5, 3), (4, 4)])
+@pytest.mark.parametrize("L,q", [(4, 3), (5, 3), (4, 4), (3, 10)])
 def test_potts_low_levels_closed_form(L, q):
     """Sum rule and the lowest levels, counted by hand on the torus: the q ordered
     states; one site of another state breaks 4 bonds (qN(q-1) states); a
     two-site domino breaks 6 when both sites share a new state (2N q(q-1)) and
     7 when they differ from each other too (2N q(q-1)(q-2)); 1, 2, 3 and 5
-    broken bonds are impossible."""
-    from oracle import exact
-
+    broken bonds are impossible.  On the 3x3 torus a whole row or column of
+    one new state also breaks just 6 bonds (2L q(q-1) more)."""
     N = L * L
-    g = _potts_golden(L, q) if (L, q) == (4, 3) else exact.potts_dos_transfer(L, q)
+    g = _potts_exact(L, q)
     assert sum(g.values()) == q ** N
     lo = -2 * N
     assert g[lo] == q
     assert all(lo + d not in g for d in (1, 2, 3, 5))
     assert g[lo + 4] == q * N * (q - 1)
-    assert g[lo + 6] == 2 * N * q * (q - 1)
+    lines = 2 * L * q * (q - 1) if L == 3 else 0
+    assert g[lo + 6] == 2 * N * q * (q - 1) + lines
     assert g[lo + 7] == 2 * N * q * (q - 1) * (q - 2)
 
 
@@ -401,14 +415,13 @@ def test_potts_converges_to_exact(oracle_lib):
     """REWL on Potts lattices beyond enumeration's reach for a test, against the
     exact DOS: 4x4 q = 3 under halving to ln f = 1e-6 (measured 0.075, 0.061 for
     seeds 1, 2); 5x5 q = 3 and 4x4 q = 4 under the 1/t rule to 1e-5 (measured
-    0.037-0.067 over seeds 1-3).  Every exactly reachable level is visited, and no
-    other."""
-    from oracle import exact
-
+    0.037-0.067 over seeds 1-3); 3x3 at the workload's q = 10 (halving 0.086,
+    1/t 0.045).  Every exactly reachable level is visited, and no other."""
     cases = [(4, 3, 3, "halving", 1e-6, 1, 0.2), (4, 3, 3, "halving", 1e-6, 2, 0.2),
-             (5, 3, 4, "1/t", 1e-5, 1, 0.1), (4, 4, 3, "1/t", 1e-5, 2, 0.1)]
+             (5, 3, 4, "1/t", 1e-5, 1, 0.1), (4, 4, 3, "1/t", 1e-5, 2, 0.1),
+             (3, 10, 2, "halving", 1e-6, 1, 0.2), (3, 10, 2, "1/t", 1e-5, 2, 0.1)]
     for L, q, h, sched, lf, seed, tol in cases:
-        g = _potts_golden(L, q) if (L, q) == (4, 3) else exact.potts_dos_transfer(L, q)
+        g = _potts_exact(L, q)
         run = oracle_lib.Run("potts", L, q=q, n_windows=h, walkers_per_window=2, lnf_final=lf,
                              S=5_000, seed=seed, schedule=sched, n_threads=4)
         assert run.run()
