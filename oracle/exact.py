@@ -11,6 +11,8 @@ These are the truth sources the oracle is pinned against (the paper compares its
   integer arithmetic (independent of the closed form below).
 * ``potts_dos_transfer``: the 2D q-state Potts DOS on an L x L torus by a row
   transfer matrix (exact while q^N < 2^53: 5 x 5 at q = 3, 4 x 4 at q = 4).
+* ``ea_dos_transfer``: the 2D +-J DOS on an L x L torus for given couplings by
+  a row transfer matrix with one matrix per row (exact for L <= 7).
 * ``ising_dos_exact``: the 2D Ising DOS on an L x L torus (L even) from
   Kaufman's closed-form partition function of the finite torus (B. Kaufman,
   Phys. Rev. 76, 1232 (1949)), turned into the integer coefficients g(E) the way
@@ -171,6 +173,65 @@ def potts_dos_transfer(L, q):
             total[v:] += V[r0, :D - v, :][:, cols].sum(1)
     out = {-u: int(n) for u, n in enumerate(total) if n}
     assert sum(out.values()) == q ** N
+    return out
+
+
+def _add_shifted(dst, src, shift, cols):
+    """dst[:, u + shift, cols] += src[:, u, cols] over every u that stays in range."""
+    D = dst.shape[1]
+    if shift >= 0:
+        dst[:, shift:, cols] += src[:, :D - shift, cols]
+    else:
+        dst[:, :D + shift, cols] += src[:, -shift:, cols]
+
+
+def ea_dos_transfer(L, couplings):
+    """Exact DOS of the 2D +-J model on the L x L torus by a row transfer matrix.
+
+    couplings: 2N values +-1, [2i] = J(i, right), [2i+1] = J(i, down), site
+    i = row * L + column; E = -sum J s s.  Row r's own bonds and its bonds to the
+    row above differ from row to row, so each added row has its own matrix; the
+    periodic closure with the first row uses the last row's downward bonds.
+    Index u = E + 2N stays in [0, 4N] for every partial sum of bonds.  The counts
+    are integers below 2^N < 2^53 (L <= 7), so the float64 products are exact.
+    Returns a dict {E: count}.
+    """
+    N = L * L
+    if N >= 53:
+        raise ValueError("counts too large for exact float64 sums")
+    J = np.asarray(couplings, dtype=np.int64).reshape(L, L, 2)      # [row, column, right/down]
+    R = 1 << L
+    spins = np.array([[1 if (a >> c) & 1 else -1 for c in range(L)] for a in range(R)])
+    nxt = np.roll(spins, -1, axis=1)
+    # energy of a row's own bonds, per row index: -sum_c J[r, c, right] s_c s_{c+1}
+    intra = [-(spins * nxt * J[r, :, 0]).sum(1) for r in range(L)]
+    # energy of the bonds from row r (state a) down to the next row (state b)
+    def inter(r):
+        return -(spins[:, None, :] * spins[None, :, :] * J[r, :, 1]).sum(2)
+
+    D = 4 * N + 1
+    V = np.zeros((R, D, R))                                           # [first row, u, last row]
+    V[np.arange(R), 2 * N + intra[0], np.arange(R)] = 1.0
+    for r in range(1, L):
+        X = inter(r - 1)
+        new = np.zeros_like(V)
+        for v in np.unique(X):
+            P = (V.reshape(R * D, R) @ (X == v).astype(np.float64)).reshape(R, D, R)
+            for h in np.unique(intra[r]):
+                _add_shifted(new, P, int(v + h), intra[r] == h)
+        V = new
+    X = inter(L - 1)                                                  # last row down to the first
+    total = np.zeros(D)
+    for r0 in range(R):
+        for v in np.unique(X[:, r0]):
+            cols = X[:, r0] == v
+            part = V[r0][:, cols].sum(1)
+            if v >= 0:
+                total[v:] += part[:D - v]
+            else:
+                total[:D + v] += part[-v:]
+    out = {u - 2 * N: int(n) for u, n in enumerate(total) if n}
+    assert sum(out.values()) == 2 ** N
     return out
 
 

@@ -56,6 +56,10 @@ MUTATIONS = {
         "(J[2 * i] * s[rt] + J[2 * lf] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * up + 1] * s[up]);",
         "(J[2 * i] * s[rt] + J[2 * i] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * up + 1] * s[up]);",
         WALK),
+    "the +-J energy change using the site's own coupling upwards": (
+        "(J[2 * i] * s[rt] + J[2 * lf] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * up + 1] * s[up]);",
+        "(J[2 * i] * s[rt] + J[2 * lf] * s[lf] + J[2 * i + 1] * s[dn] + J[2 * i + 1] * s[up]);",
+        "ea_converges_to_exact"),
     "the Potts energy change with its sign flipped": (
         "return (int64_t)same_old - same_new;",
         "return (int64_t)same_new - same_old;", WALK),

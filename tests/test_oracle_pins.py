@@ -431,6 +431,51 @@ def test_potts_converges_to_exact(oracle_lib):
         assert _max_err(lng, ref) < tol, (L, q, sched, seed, _max_err(lng, ref))
 
 
+def test_ea_transfer_matrix_agrees_with_enumeration():
+    """The +-J transfer matrix (one matrix per row, since the couplings change
+    from row to row) equals enumeration on 3x3 and 4x4 instances, and with every
+    coupling +1 equals Kaufman's Ising DOS (4x4, 6x6)."""
+    from oracle import exact
+    from workloads import ea_couplings
+
+    for L in (3, 4):
+        for seed in (1, 2, 3):
+            J = ea_couplings(L, seed)
+            assert exact.ea_dos_transfer(L, J) == exact.brute_dos("ea", L, couplings=J)
+    for L in (4, 6):
+        N = L * L
+        ising = exact.ising_dos_exact(L)
+        assert exact.ea_dos_transfer(L, np.ones(2 * N, np.int8)) == \
+            {-2 * N + 4 * j: n for j, n in enumerate(ising) if n}
+
+
+@pytest.mark.parametrize("L", [5, 6])
+def test_ea_converges_to_exact(oracle_lib, L):
+    """REWL on +-J instances beyond the enumerated 4x4 against the transfer-matrix
+    DOS (5x5: odd, no E -> -E symmetry; 6x6: symmetric), range |E| <= 1.5 N, so
+    the lowest visited level is the reference (ln g = 0 there).  Measured max
+    errors, halving to ln f = 1e-6: 0.17, 0.09 (5x5), 0.12, 0.25 (6x6)."""
+    from oracle import exact
+    from workloads import ea_couplings
+
+    N = L * L
+    J = ea_couplings(L, 1)
+    g = exact.ea_dos_transfer(L, J)
+    assert sum(g.values()) == 2 ** N
+    n_neg = int((J < 0).sum())
+    assert all((e + 2 * N - 2 * n_neg) % 4 == 0 for e in g)
+    if L % 2 == 0:
+        assert all(g.get(-e) == n for e, n in g.items())
+    for seed in (1, 2):
+        run = oracle_lib.Run("ea", L, couplings=J, e_min=-(3 * N) // 2, e_max=(3 * N) // 2,
+                             n_windows=4, walkers_per_window=2, lnf_final=1e-6, S=5_000,
+                             seed=seed, n_threads=4)
+        assert run.run()
+        ref = np.array([math.log(g[e]) if e in g else -np.inf for e in run.energies()])
+        ref = ref - ref[np.isfinite(ref)][0]
+        assert _max_err(run.lng(), ref) < 0.35, (L, seed, _max_err(run.lng(), ref))
+
+
 def test_brute_force_ea_symmetry():
     """On an even torus g(E) = g(-E) for any +-J couplings (flip one sublattice)."""
     from oracle import exact
