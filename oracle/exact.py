@@ -13,6 +13,8 @@ These are the truth sources the oracle is pinned against (the paper compares its
   transfer matrix (exact while q^N < 2^53: 5 x 5 at q = 3, 4 x 4 at q = 4).
 * ``ea_dos_transfer``: the 2D +-J DOS on an L x L torus for given couplings by
   a row transfer matrix with one matrix per row (exact for L <= 7).
+* ``ea3_dos_layers``: the 3D +-J DOS on the 3 x 3 x 3 torus by summing over
+  its three layers (independent of enumeration).
 * ``ising_dos_exact``: the 2D Ising DOS on an L x L torus (L even) from
   Kaufman's closed-form partition function of the finite torus (B. Kaufman,
   Phys. Rev. 76, 1232 (1949)), turned into the integer coefficients g(E) the way
@@ -233,6 +235,49 @@ def ea_dos_transfer(L, couplings):
     out = {u - 2 * N: int(n) for u, n in enumerate(total) if n}
     assert sum(out.values()) == 2 ** N
     return out
+
+
+def ea3_dos_layers(couplings):
+    """Exact DOS of the 3D +-J model on the 3 x 3 x 3 torus by summing over its
+    three layers z = 0, 1, 2 (512 states each).
+
+    couplings: 3N values +-1, [3i + a] = J(i, next site along axis a = x, y, z),
+    site i = (z L + y) L + x; E = -sum J s s.  E splits into each layer's own
+    bonds (x and y), and the z bonds from layer 0 to 1, 1 to 2 and 2 back to 0.
+    For every pair (layer 0, layer 2) the middle layer's sum is a polynomial in
+    its energy, built from 0/1 matrices grouped by energy value; the ends are
+    added last.  Counts are integers below 2^27, exact in float64.  Returns a
+    dict {E: count}.
+    """
+    L = 3
+    N = L ** 3
+    J = np.asarray(couplings, dtype=np.int64).reshape(L, L, L, 3)   # [z, y, x, axis]
+    S = 1 << (L * L)
+    lay = np.array([[1 if (a >> j) & 1 else -1 for j in range(L * L)] for a in range(S)])
+    lay = lay.reshape(S, L, L)                                         # [state, y, x]
+    xn = np.roll(lay, -1, axis=2)
+    yn = np.roll(lay, -1, axis=1)
+    intra = [-(lay * xn * J[z, :, :, 0] + lay * yn * J[z, :, :, 1]).sum((1, 2))
+             for z in range(L)]
+    inter = [-(lay[:, None] * lay[None, :] * J[z, :, :, 2]).sum((2, 3)) for z in range(L)]
+    M = 2 * L * L + 2 * L * L                                          # bonds in the middle sum
+    P = np.zeros((S, S, 2 * M + 1))                                    # [layer 0, layer 2, m + M]
+    for h in np.unique(intra[1]):
+        cols = intra[1] == h
+        for v1 in np.unique(inter[0][:, cols]):
+            A = (inter[0][:, cols] == v1).astype(np.float64)
+            for v2 in np.unique(inter[1][cols, :]):
+                B = (inter[1][cols, :] == v2).astype(np.float64)
+                P[:, :, int(h + v1 + v2) + M] += A @ B
+    Q = intra[0][:, None] + intra[2][None, :] + inter[2].T             # [layer 0, layer 2]
+    total = {}
+    for t in np.unique(Q):
+        part = P[Q == t].sum(0)
+        for m in np.flatnonzero(part):
+            e = int(t) + int(m) - M
+            total[e] = total.get(e, 0) + int(part[m])
+    assert sum(total.values()) == 2 ** N
+    return total
 
 
 def ising_dos_exact(L, extra_digits=40):

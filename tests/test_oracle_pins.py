@@ -883,6 +883,41 @@ def test_ea3_golden_3x3x3(oracle_lib):
     assert _max_err(run.lng(), ref) < 0.15
 
 
+def test_ea3_layer_sum_agrees_with_enumeration():
+    """A second exact method for the 3x3x3 glass, summing over its three layers,
+    reproduces the stored enumeration; with every coupling +1 (the 3D Ising
+    torus) its lowest levels are the hand counts: 2 ground states, 2N single
+    flips (6 broken bonds, E + 12), 2 x 3N dominoes (10 broken bonds, E + 20) and
+    nothing between."""
+    from oracle import exact
+    from workloads import ea3_couplings
+
+    assert exact.ea3_dos_layers(ea3_couplings(3, 1)) == _load_ea3_golden()
+    N = 27
+    g = exact.ea3_dos_layers(np.ones(3 * N, np.int8))
+    lo = -3 * N
+    assert g[lo] == 2 and g[lo + 12] == 2 * N and g[lo + 20] == 2 * 3 * N
+    assert all(lo + d not in g for d in (4, 8, 16))
+
+
+@pytest.mark.parametrize("coupling_seed", [2, 3])
+def test_ea3_converges_to_layer_sum(oracle_lib, coupling_seed):
+    """REWL on two more 3x3x3 glasses against their exact DOS from the layer sum
+    (4 windows x 4 walkers, ln f to 1e-6; measured 0.055-0.087)."""
+    from oracle import exact
+    from workloads import ea3_couplings
+
+    J = ea3_couplings(3, coupling_seed)
+    g = exact.ea3_dos_layers(J)
+    n_neg = int((J < 0).sum())
+    assert all((e - (-81 + 2 * n_neg)) % 4 == 0 for e in g)
+    run = oracle_lib.Run("ea3", 3, couplings=J, n_windows=4, walkers_per_window=4, S=5000,
+                         lnf_final=1e-6, seed=1, n_threads=4)
+    assert run.run()
+    ref = np.array([math.log(g[e]) if e in g else -np.inf for e in run.energies()])
+    assert _max_err(run.lng(), ref) < 0.15
+
+
 def test_invalid_arguments(oracle_lib):
     from workloads import ea3_couplings
 
