@@ -330,3 +330,93 @@ def test_load_survives_corrupted_fields(tmp_path, rewl, oracle_lib):
         assert rewl.lib().rewl_last_error()
         seen.add(rc)
     assert seen == {-1, -5}
+
+
+def test_random_parameters_validate_like_the_oracle(rewl, oracle_lib):
+    """Random small runs with up to two fields pushed to edge or invalid values
+    (NaN and boundary overlaps and flatness, non-positive ln f, zero attempts,
+    too many windows, empty or inverted energy ranges, q and L out of range,
+    couplings that are not +-1, unknown schedules): the library's host
+    validation refuses exactly the sets the oracle refuses (code -1 on both
+    sides).  Small lattices keep every accepted window inside the LDS limit,
+    which the oracle does not have; more than 64 walkers per window is the
+    library's own limit and refused there alone."""
+    from workloads import ea3_couplings, ea_couplings
+
+    rng = np.random.default_rng(31)
+    nan = float("nan")
+    perturb = {
+        "overlap": [nan, 0.0, 1.0, 1e-3, 0.5, 0.999],
+        "flatness": [nan, 0.0, 1.0, 1.0001, 0.5],
+        "lnf_init": [0.0, -1.0, 1e-12, 2.0],
+        "lnf_final": [0.0, -1e-8, 1e-12, 3.0],
+        "S": [0, -5, 1, 7],
+        "n_windows": [0, -1, 1, 2, 5, 9, 40],
+        "walkers_per_window": [0, 1, 3, 64, 65],
+        "e_min": [-10 ** 6, -3, 0, 5, 40],
+        "e_max": [10 ** 6, 5, 0, -3, -40],
+        "schedule": [2, -1],
+        "bad_coupling": [0, 2, -2],
+        "L": [2, 257, 1],
+        "q": [1, 0, 128, 127],
+    }
+    models = ["ising", "potts", "ea", "ea3"]
+    disagree = []
+    n_ok = n_bad = 0
+    for it in range(300):
+        model = models[it % 4]
+        L = int(rng.integers(2, 4)) if model == "ea3" else int(rng.integers(3, 9))
+        kw = dict(model=model, L=L, n_windows=int(rng.integers(1, 4)),
+                  walkers_per_window=int(rng.integers(1, 3)), S=100, seed=int(it))
+        if model == "potts":
+            kw["q"] = int(rng.integers(2, 6))
+        fields = rng.choice(sorted(perturb), size=int(rng.integers(0, 3)), replace=False)
+        sched = None
+        for f in fields:
+            v = perturb[f][int(rng.integers(len(perturb[f])))]
+            if f == "schedule":
+                sched = v
+            elif f != "bad_coupling":
+                kw[f] = v
+        if kw["L"] < 1 or (model != "ea3" and kw["L"] > 256) or kw["L"] > 64:
+            L_cpl = 3
+        else:
+            L_cpl = kw["L"]
+        if model == "ea":
+            kw["couplings"] = ea_couplings(L_cpl, it)
+        elif model == "ea3":
+            kw["couplings"] = ea3_couplings(L_cpl, it)
+        if "bad_coupling" in fields and model in ("ea", "ea3"):
+            kw["couplings"] = kw["couplings"].copy()
+            kw["couplings"][int(rng.integers(kw["couplings"].size))] = perturb["bad_coupling"][it % 3]
+        if L_cpl != kw["L"]:
+            continue    # couplings of the documented length cannot be made for this L
+        p, keep = rewl.make_params(**kw)
+        dev, lds = C.c_size_t(), C.c_size_t()
+        if sched is not None:
+            # an unknown schedule number (the Python bindings only pass known names)
+            p.schedule = sched
+            assert rewl.lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)) == -1
+            n_bad += 1
+            continue
+        r = rewl.lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds))
+        if kw["walkers_per_window"] > 64:
+            # the library's own limit: the exchange step keeps a window pair's
+            # partner permutation in 64-entry work-group arrays
+            assert r == -1 and b"walkers_per_window" in rewl.lib().rewl_last_error()
+            n_bad += 1
+            continue
+        try:
+            oracle_lib.Run(**kw)
+            o = 0
+        except oracle_lib.OracleError as e:
+            o = e.code
+        if (o == -1) != (r == -1):
+            disagree.append((kw, o, r, rewl.lib().rewl_last_error()))
+        if r == 0:
+            n_ok += 1
+            assert 0 < lds.value <= 160 * 1024
+        else:
+            n_bad += 1
+    assert not disagree, disagree[:3]
+    assert n_ok > 50 and n_bad > 50, (n_ok, n_bad)
