@@ -65,3 +65,46 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
         assert "exactly one GPU" in r.stderr and "--gpus 1" in r.stderr
         assert r.stdout == ""
 
+
+
+def test_profile_commands_run_committed_files_within_counter_limits():
+    """Every rocprofv3 command recorded in profiles/ runs bench.py (a committed
+    file) with arguments bench.py accepts, puts the program right after `--`,
+    and keeps each counter pass within one pass's hardware limits (at most 8 SQ
+    and 2 GRBM counters, FETCH_SIZE and WRITE_SIZE in passes of their own) and
+    free of trace domains."""
+    import glob
+    import os
+    import shlex
+    import subprocess
+    import sys
+
+    from conftest import ROOT
+
+    cmds = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        cmds += [(path, line.strip()) for line in open(path)
+                 if line.strip().startswith("rocprofv3 ")]
+    assert len(cmds) >= 10
+    for path, line in cmds:
+        argv = shlex.split(line)
+        prog = argv[argv.index("--") + 1:]
+        assert prog[:2] == ["python3", "bench.py"], (path, line)
+        opts = argv[1:argv.index("--")]
+        for bad in ("-s", "--sys-trace", "-r", "--runtime-trace", "--hip-trace", "--hsa-trace"):
+            assert not ("--pmc" in opts and bad in opts), (path, line)
+        if "--pmc" in opts:
+            i = opts.index("--pmc") + 1
+            counters = []
+            while i < len(opts) and not opts[i].startswith("-"):
+                counters.append(opts[i])
+                i += 1
+            assert sum(c.startswith("SQ_") for c in counters) <= 8, line
+            assert sum(c.startswith("GRBM_") for c in counters) <= 2, line
+            assert not ({"FETCH_SIZE", "WRITE_SIZE"} <= set(counters)), line
+        # bench.py parses the arguments (then stops at the one-GPU check, before
+        # any GPU work): an unknown or malformed argument would exit with "error:"
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *prog[2:],
+                            "--gpus", "2"], capture_output=True, text=True, timeout=120, cwd=ROOT)
+        assert r.returncode == 2 and "error:" not in r.stderr and "exactly one GPU" in r.stderr, \
+            (path, line, r.stderr[-500:])
