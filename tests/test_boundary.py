@@ -420,3 +420,33 @@ def test_random_parameters_validate_like_the_oracle(rewl, oracle_lib):
             n_bad += 1
     assert not disagree, disagree[:3]
     assert n_ok > 50 and n_bad > 50, (n_ok, n_bad)
+
+
+def test_last_error_is_per_thread(rewl):
+    """rewl_last_error describes the calling thread's last failure: two threads
+    failing validation for different reasons at the same time (ctypes releases
+    the interpreter lock during the calls) each read back their own message."""
+    import threading
+
+    cases = {"L": (dict(model="ising", L=2), b"L must"),
+             "q": (dict(model="potts", L=8, q=1), b"q must")}
+    bad = []
+    barrier = threading.Barrier(2)
+
+    def work(name):
+        kw, want = cases[name]
+        p, keep = rewl.make_params(**kw)
+        dev, lds = C.c_size_t(), C.c_size_t()
+        barrier.wait()
+        for _ in range(20000):
+            if rewl.lib().rewl_footprint(C.byref(p), C.byref(dev), C.byref(lds)) != -1 or \
+                    want not in rewl.lib().rewl_last_error():
+                bad.append(name)
+                return
+
+    ts = [threading.Thread(target=work, args=(n,)) for n in cases]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not bad, bad
