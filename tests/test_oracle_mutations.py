@@ -100,6 +100,12 @@ MUTATIONS = {
     "the 1/t increment taken as W/(t+1)": (
         "if (one_over_t) lnf = Wd / (double)run->t[w];",
         "if (one_over_t) lnf = Wd / (double)(run->t[w] + 1);", "one_over_t_increments"),
+    "the partner shuffle never leaving a walker in place": (
+        "int j = (int)mulhi32(next_word(&ws), (uint32_t)(a + 1));",
+        "int j = (int)mulhi32(next_word(&ws), (uint32_t)(a));", "exchange_partner_is_uniform"),
+    "exchange partners paired by slot instead of by the permutation": (
+        "int wi = k * m + a, wj = (k + 1) * m + perm[a];",
+        "int wi = k * m + a, wj = (k + 1) * m + a;", "exchange_partner_is_uniform"),
     "the 1/t rule never switched on": (
         "if (run->schedule == 1 && run->lnf[k] < Wt) {",
         "if (run->schedule == 2 && run->lnf[k] < Wt) {", "one_over_t_schedule"),

@@ -603,6 +603,64 @@ def test_exchange_pairs_alternate(oracle_lib):
         prev = now
 
 
+def _observed_partners(oracle_lib, m, rounds, seed):
+    """Partner permutations of the exchange step, read off a run in which every
+    exchange is accepted: two windows that both cover every level the walk can
+    reach from random spins (6x6 Ising, overlap 0.95: bins [0, 35] and [1, 36],
+    which leave out only the two ordered states), ln f = 1e-30 so that every Eq. (1) log-ratio is far above any
+    ln u (<= ln(1 - 2^-53)), flatness 1 so that merges stay rare, one attempt per
+    walker per round.  In an even round (pair (0, 1)) walker a of window 0 hands
+    its configuration to walker pi[a] of window 1; after one attempt each
+    configuration is within one flipped spin of what it was before the round,
+    which identifies pi[a]."""
+    run = oracle_lib.Run("ising", 6, n_windows=2, walkers_per_window=m, overlap=0.95,
+                         flatness=1.0, lnf_init=1e-30, lnf_final=1e-300, S=1, seed=seed)
+    win = [run.window(k) for k in range(2)]
+    assert (win[0]["lo"], win[0]["hi"], win[1]["lo"], win[1]["hi"]) == (0, 35, 1, 36)
+    perms = []
+    for r in range(rounds):
+        before = [run.walker(w)["spins"].copy() for w in range(2 * m)]
+        run.step(1)
+        if r % 2:
+            continue
+        after = [run.walker(w)["spins"] for w in range(2 * m)]
+        pi = []
+        for a in range(m):
+            hits = [b for b in range(m) if np.sum(after[m + b] != before[a]) <= 1]
+            pi.append(hits[0] if len(hits) == 1 else None)
+        if None not in pi:
+            perms.append(tuple(pi))
+    return perms, run.stats()
+
+
+@pytest.mark.parametrize("m,rounds", [(2, 800), (3, 2400), (4, 4800)])
+def test_exchange_partner_is_uniform(oracle_lib, m, rounds):
+    """The paper lets each walker pick its exchange partner in the neighbouring
+    window at random (parallel-scheme paragraph).  The partners of one exchange
+    step form a permutation of the m walkers of the upper window; every one of the
+    m! permutations must come out equally often.  Chi-square over the observed
+    permutations, p > 1e-6.  (A shuffle that never leaves an element in place
+    yields only the (m-1)! cyclic orders; pairing a with a yields the identity.)"""
+    import itertools
+
+    from scipy import stats
+
+    perms = []
+    ex = 0
+    for seed in (3, 4):
+        p, st = _observed_partners(oracle_lib, m, rounds // 2, seed)
+        perms += p
+        ex += st["ex_acc"]
+    n_pairs = 2 * (rounds // 4) * m
+    assert ex == n_pairs and len(perms) > 0.99 * (n_pairs // m), (ex, n_pairs, len(perms))
+    for p in perms:
+        assert sorted(p) == list(range(m)), p
+    cats = list(itertools.permutations(range(m)))
+    counts = np.array([perms.count(c) for c in cats], dtype=float)
+    chi2, pval = stats.chisquare(counts)
+    assert pval > 1e-6, (m, counts, chi2, pval)
+
+
 @pytest.mark.parametrize("model,q,L", [("ising", 2, 6), ("potts", 3, 5), ("ea", 2, 6)])
 def test_walkers_stay_in_their_windows(oracle_lib, model, q, L):
     """A move or an exchange that would take a walker out of its window is
