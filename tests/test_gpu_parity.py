@@ -155,6 +155,48 @@ def test_one_over_t_rounds_bitexact(gpu, orc, name, kw, steps):
     assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
 
 
+WIDE = [
+    # windows wider than the 256 threads of the flatness/merge work-group, so
+    # its reductions and its merge loop take two or three strides; flatness 0.5
+    # and ln f_final 0.1 give four merges per window (flags set, cleared, set
+    # again) within a few hundred to a few thousand rounds
+    ("ising24_368bins", dict(model="ising", L=24, n_windows=2, walkers_per_window=2, S=5000,
+                             e_min=-1100, e_max=1100, overlap=0.5, flatness=0.5, lnf_final=0.1,
+                             seed=21), (1, 60, 300)),
+    ("potts16q10_343bins", dict(model="potts", L=16, q=10, n_windows=2, walkers_per_window=2,
+                                S=5000, overlap=0.5, flatness=0.5, lnf_final=0.1, seed=22),
+     (1, 250, 1300)),
+    ("ising32_676bins_h1", dict(model="ising", L=32, n_windows=1, walkers_per_window=2, S=5000,
+                                e_min=-1300, e_max=1400, flatness=0.5, lnf_final=0.1, seed=23),
+     (1, 400, 200)),
+]
+
+
+@pytest.mark.parametrize("name,kw,steps", WIDE, ids=[c[0] for c in WIDE])
+def test_wide_windows_bitexact(gpu, orc, name, kw, steps):
+    """Windows of 343 to 676 bins through several merges to convergence: every
+    walker's state after each checkpoint, then the stitched ln g."""
+    g, o = _pair(gpu, orc, **kw)
+    widths = [w["hi"] - w["lo"] + 1 for w in o.windows()]
+    assert min(widths) > 256, widths
+    done_rounds = 0
+    for rounds in steps:
+        g.step(rounds)
+        o.step(rounds)
+        done_rounds += rounds
+        assert_same_state(g, o, f"{name} after {done_rounds} rounds")
+    assert any(f >= 0 for f in o.first_merge()), "no window merged yet"
+    ok_g, rounds_g = g.run()
+    assert ok_g and o.run()
+    assert rounds_g == max(w["finish_round"] for w in o.windows()) + 1
+    assert_same_state(g, o, f"{name} converged")
+    assert all(w["lnf"] == 0.0625 for w in o.windows())   # four merges: 1 -> 1/16
+    lg, lo = g.lng(), o.lng()
+    fin = np.isfinite(lo)
+    assert np.array_equal(np.isfinite(lg), fin)
+    assert np.array_equal(lg[fin].view(np.uint64), lo[fin].view(np.uint64))
+
+
 @pytest.mark.parametrize("model,L,q", [("ising", 8, 2), ("potts", 6, 4)])
 def test_balanced_partition_run_bitexact(gpu, orc, model, L, q):
     """Run-time balanced windows: the pre-run's first-merge rounds agree with
@@ -252,31 +294,42 @@ def test_largest_lattice_bitexact(gpu, orc):
 
 def test_concurrent_use_is_refused(gpu):
     """A second host thread calling into a run while the first is stepping it
-    gets REWL_EBUSY; the run is unaffected and usable afterwards."""
+    gets REWL_EBUSY; the run is unaffected and usable afterwards.  The first
+    thread signals right before it enters a long call (3000 rounds, about 3 s);
+    the second polls a read-only call (which changes nothing when it gets in
+    first) until it is refused, while the first is still inside."""
     import threading
-    import time
 
     r = gpu.Run("ising", 32, n_windows=16, walkers_per_window=4, seed=41)
     r.step(1)
     errors = []
+    entering = threading.Event()
 
-    def long_step():
+    def long_run():
         try:
-            r.run(300)         # ~0.3 s: rounds in chunks, waiting on each
+            entering.set()
+            r.run(3000)
         except gpu.RewlError as e:
             errors.append(e)
 
-    th = threading.Thread(target=long_step)
+    th = threading.Thread(target=long_run)
     th.start()
-    time.sleep(0.05)
-    with pytest.raises(gpu.RewlError) as e:
-        r.step(1)
-    assert e.value.code == -6
+    assert entering.wait(30)
+    refused = None
+    for _ in range(100_000):
+        try:
+            r.info()
+        except gpu.RewlError as e:
+            refused = e
+            break
+        if not th.is_alive():
+            break
+    assert refused is not None and refused.code == -6, "no REWL_EBUSY while the run was busy"
     th.join()
     assert not errors
-    assert r.info()["rounds"] == 301
+    assert r.info()["rounds"] == 3001
     r.step(1)
-    assert r.info()["rounds"] == 302
+    assert r.info()["rounds"] == 3002
     r.close()
 
 
