@@ -1,35 +1,42 @@
 #!/usr/bin/env python3
 """Benchmark: replica-exchange Wang-Landau on one MI355X.
 
-One step = one complete REWL run of the workload (default: 2D Ising 32x32,
-16 windows x 4 walkers): start-up on the device, rounds until every window has
-reached ln f_final, stitching of ln g on the host; fresh seed per step.
+Headline (the JSON line's `value`): the batched spin-glass workload, 256
+independent 2D +-J Edwards-Anderson glasses L = 24 (couplings +-1 with p = 1/2,
+one coupling seed per instance), 8 windows x 4 walkers each, overlap 0.75,
+flatness 0.8, ln f 1 -> 1e-6, 10^4 attempts per walker between exchange steps.
+One step = one round of every run: 8192 walkers x 10^4 sweep attempts, then
+flatness, merges and one exchange step.  `value` = sweep attempts (accepted or
+not; start-up excluded) per second of wall clock over the K timed steps, after
+W untimed ones; the launch form (per-round kernels, or one persistent
+work-group per run looping the rounds in LDS) and the walkers per wave come
+from the package's autotuner unless given.
 
-Reported on one JSON line:
-  value         sweep attempts per second (every attempt, accepted or not,
-                start-up excluded) over the timed plain steps, wall clock;
-  time_to_dos_s p50 / p99 seconds from creation to the stitched ln g on the
-                host, plain form;
-  batched       the same workload, `--batch` seeds at once in one batch
-                (walkers per wave chosen by the autotuner): aggregate
-                attempts/s and per-run time-to-DOS p50 / p99;
-  max_abs_dlng_vs_exact  per step, max |ln g - ln g_exact| over the bins
-                (Ising sizes with a stored exact DOS);
-  batched_glasses  256 independent 24x24 +-J glasses, 8 windows x 4 walkers
-                each, in one batch, walkers per wave and attempts between
-                exchanges autotuned: attempts/s over a fixed number of attempts
-                and the sweep kernel's roofline (same definition as below);
-  roofline      the sweep kernel's VALU work per attempt times its attempts,
-                over its own time measured with HIP events recorded on the run's
-                stream around each sweep launch, against the MI355X vector-ALU
-                peak;
-  cpu_baseline  the CPU oracle on the same workload, all host cores, on a
-                bounded sample of rounds; its time-to-DOS is extrapolated
-                exactly: the oracle is bit-identical to the GPU run, so it makes
-                the same rounds with the same windows active, and its OpenMP
-                static schedule gives each round's time from the per-thread
-                rate.
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ising32]
+  roofline      the dominant kernel of the timed steps (the persistent kernel,
+                or the sweep kernel of the per-round form): VALU lane-slots per
+                sweep attempt (170, the upper end of the algorithmic 150-170
+                estimate for the model with couplings) x attempts per launch,
+                over the launch's average duration from HIP events recorded on
+                the batch's stream around each launch, against 256 CUs x 4
+                SIMDs x 16 lanes x 2.4 GHz; traffic = HBM bytes per launch from
+                the committed rocprofv3 counter summary while the device
+                sources are unchanged (null otherwise);
+  cpu_baseline  the CPU oracle on the same workload (a few of the instances,
+                a few rounds each), all host threads; single-core and all-core
+                rates for the other workloads under `per_workload`;
+  legs          bounded sub-measurements, each with its own wall-clock budget:
+                the other launch form at the same setting; the 32x32 Ising and
+                64x64 q=10 Potts single runs (attempts/s over rounds with every
+                window running, sweep kernel time); p50/p99 time-to-converged
+                ln g of the 8x8 Ising workload over 20 seeds arriving together:
+                plain runs one after another (each run's own duration, and its
+                completion time counting the runs before it) vs all 20 in one
+                batch (autotuned launch setting).
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form auto|rounds|persistent]
+                       [--walkers-per-wave P] [--legs all|headline] [--no-cpu]
+Other modes (one JSON line each): --rounds R (profile: fixed rounds of one
+workload), --served N, --balanced, --errors R, --copy-mb M (counter
+calibration).
 """
 from __future__ import annotations
 
@@ -43,11 +50,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU lane-slots one sweep attempt needs (Ising; quarter-rate 32-bit
-# multiplies count 4): Philox4x32-10 100, site draw 4, ln u 50, neighbours 20,
-# the accept/update chain 20; the glasses add the coupling terms, the 3D one
-# two more neighbours.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_SLOTS_PER_ATTEMPT = {"ising": 194, "ea": 200, "potts": 204, "ea3": 212}
+# VALU lane-slots one sweep attempt needs, the algorithmic estimate (quarter-
+# rate 32-bit multiplies count 4): Philox4x32-10 ~100-110, site 4, neighbours
+# and energy change ~20, the decision 2, the acceptance function ~16, updates
+# ~5: 150-170; the upper end is taken for every model.  This implementation
+# spends ~194-212 (it draws ln u, ~50 slots, for every attempt; reported beside
+# it as the recount).  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_SLOTS_PER_ATTEMPT = 170
+VALU_SLOTS_RECOUNT = {"ising": 194, "ea": 200, "potts": 204, "ea3": 212}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOAD_TEXT = {
@@ -62,6 +72,9 @@ WORKLOAD_TEXT = {
     "ea3d12": "3D +-J EA glass 12x12x12 periodic, 8 windows x 4 walkers, overlap 0.75, "
               "flatness 0.8, ln f 1 -> 1e-6, 1e4 attempts/walker/round",
 }
+HEADLINE = ("256 independent 2D +-J EA glasses L=24 periodic (couplings +-1, p=0.5, seeds "
+            "1-256), 8 windows x 4 walkers each, overlap 0.75, flatness 0.8, ln f 1 -> 1e-6, "
+            "1e4 attempts/walker between exchanges; one step = one round of all 256 runs")
 
 
 def log(*a):
@@ -84,10 +97,10 @@ def kernel_sources_hash():
 
 
 def profiled_traffic(tag):
-    """HBM bytes per sweep launch from profiles/sweep_<tag>.md (FETCH_SIZE and
-    WRITE_SIZE scaled by a device copy of known size), or None when the file is
-    missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{tag}.md")
+    """HBM bytes per launch of the profiled kernel from profiles/<tag>.md
+    (FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size), or None
+    when the file is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{tag}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -102,14 +115,6 @@ def profiled_traffic(tag):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def sweep_kernel_name(P, waves):
-    """The sweep instantiation a launch of `waves` waves runs: the per-step bin
-    records sit in registers when waves outnumber the compute units."""
-    import torch
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    return f"sweep_kernel<{P}, {'true' if waves > cus else 'false'}>"
-
-
 def percentile(xs, q):
     import numpy as np
 
@@ -121,6 +126,85 @@ def run_kwargs(p):
             "walkers_per_window", "flatness", "lnf_init", "lnf_final", "S", "seed", "schedule",
             "windows")
     return {k: p[k] for k in keys if k in p}
+
+
+class Budget:
+    """Wall-clock allowance of the optional legs: a leg runs only while the
+    time spent so far leaves its own allowance."""
+
+    def __init__(self, total_s):
+        self.t0 = time.perf_counter()
+        self.total = total_s
+
+    def left(self):
+        return self.total - (time.perf_counter() - self.t0)
+
+    def allows(self, need_s, name):
+        if self.left() >= need_s:
+            return True
+        log(f"leg {name}: skipped ({self.left():.0f} s of the budget left, needs {need_s:.0f} s)")
+        return False
+
+
+def roofline(attempts, launches, launch_ms, traffic, kernel):
+    """VALU roofline of the dominant kernel from its HIP-event launch times."""
+    if launches <= 0 or launch_ms <= 0:
+        return None
+    per_launch = attempts / launches
+    avg_s = launch_ms * 1e-3 / launches
+    achieved = VALU_SLOTS_PER_ATTEMPT * per_launch / avg_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "kernel": kernel,
+            "launch_avg_us": avg_s * 1e6, "attempts_per_launch": per_launch,
+            "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT,
+            "frac_at_recount": achieved / VALU_PEAK_TOPS * VALU_SLOTS_RECOUNT["ea"] /
+            VALU_SLOTS_PER_ATTEMPT,
+            "valu_slots_recount": VALU_SLOTS_RECOUNT["ea"]}
+
+
+def kernel_name(rewl, form, P, waves):
+    """The instantiation a launch runs: the per-step bin records sit in
+    registers when waves outnumber the compute units."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rp = "true" if waves > cus else "false"
+    return f"persist_kernel<{P}, {rp}>" if form == "persistent" else f"sweep_kernel<{P}, {rp}>"
+
+
+def attempts_of(views):
+    return sum(v.info()["attempts"] for v in views)
+
+
+def glass_runs(n, S=10_000):
+    from workloads import run_params
+
+    return [dict(run_kwargs(run_params("ea24", seed=1 + i)), S=S) for i in range(n)]
+
+
+def timed_batch(rewl, runs, setting, steps, warmup):
+    """W untimed rounds, then K rounds bracketed by device synchronisations,
+    with HIP events around each launch of the dominant kernel."""
+    import torch
+
+    b = rewl.Batch(runs, walkers_per_wave=setting.walkers_per_wave,
+                   graph_rounds=setting.graph_rounds, form=setting.form)
+    views = [b[i] for i in range(len(runs))]
+    b.set_timing(True)
+    if warmup:
+        b.step(warmup)
+    torch.cuda.synchronize()
+    ms0, n0 = b.timing()
+    a0 = attempts_of(views)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = b.timing()
+    att = attempts_of(views) - a0
+    b.close()
+    return dict(wall=wall, attempts=att, launch_ms=ms - ms0, launches=n - n0)
 
 
 def gpu_full_run(rewl, p, max_rounds):
@@ -176,151 +260,6 @@ def exact_error(p, lng):
     return float(np.abs(lng[fin] - ref[fin]).max())
 
 
-def gpu_glasses(rewl, n_runs, rounds, candidates=(4, 8), s_candidates=(1000, 10_000, 100_000)):
-    """The batched glass workload: n_runs independent 24x24 +-J instances in one
-    batch.  The autotuner picks walkers per wave from `candidates` and attempts
-    per walker between exchanges from `s_candidates` by attempts/s over the same
-    number of attempts (4e4 per walker) each; then `rounds` x 1e4 attempts per
-    walker are timed at the chosen setting.  Returns throughput, the setting and
-    the sweep kernel's own time."""
-    import torch
-
-    from workloads import run_params
-
-    def make(P, S):
-        runs = [dict(run_kwargs(run_params("ea24", seed=1 + i)), S=S) for i in range(n_runs)]
-        return rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
-
-    def measure(b, S, attempts_per_walker):
-        b.step(1)
-        torch.cuda.synchronize()
-        a0 = sum(b[i].info()["attempts"] for i in range(n_runs))
-        t0 = time.perf_counter()
-        b.step(max(1, attempts_per_walker // S))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return (sum(b[i].info()["attempts"] for i in range(n_runs)) - a0) / dt
-
-    best, best_rate = None, -1.0
-    for S in s_candidates:
-        for P in candidates:
-            b = make(P, S)
-            rate = measure(b, S, 40_000)
-            b.close()
-            log(f"autotune: glasses P={P} S={S}: {rate / 1e9:.2f} G attempts/s")
-            if rate > best_rate:
-                best, best_rate = (P, S), rate
-    P, S = best
-    b = make(P, S)
-    b.set_timing(True)
-    b.step(1)
-    torch.cuda.synchronize()
-    a0 = sum(b[i].info()["attempts"] for i in range(n_runs))
-    ms0, n0 = b.timing()
-    t0 = time.perf_counter()
-    b.step(max(1, rounds * 10_000 // S))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms, n = b.timing()
-    att = sum(b[i].info()["attempts"] for i in range(n_runs)) - a0
-    b.close()
-    return dict(P=P, S=S, attempts=att, wall=wall, sweep_ms=ms - ms0, launches=n - n0)
-
-
-def gpu_batched(rewl, params, walkers_per_wave, graph_rounds, max_rounds):
-    """All runs in one batch; a run's time-to-DOS is the wall clock once the
-    first poll that sees it done has its stitched ln g on the host."""
-    import numpy as np
-    import torch
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=walkers_per_wave,
-                   graph_rounds=graph_rounds)
-    done_at = [None] * len(params)
-    lngs = [None] * len(params)
-    issued, chunk = 0, 64
-    while issued < max_rounds:
-        b.step(chunk)
-        issued += chunk
-        d = b.done()
-        for i in np.nonzero(d)[0]:
-            if done_at[i] is None:
-                lngs[i] = b[int(i)].lng()
-                done_at[i] = time.perf_counter() - t0
-        if d.all():
-            break
-        if issued % 8192 == 0:
-            log(f"  ... batched: {issued} rounds, {int(d.sum())}/{len(params)} runs done")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    attempts = sum(b[i].info()["attempts"] for i in range(len(params)))
-    b.close()
-    return dict(wall=wall, attempts=attempts, done_at=done_at, lng=lngs)
-
-
-def autotune(rewl, params, candidates=(1, 2, 4, 8), rounds=6):
-    """Walkers per wave with the highest attempts/s over a few rounds of this
-    batch (results do not depend on the choice)."""
-    import torch
-
-    best, best_rate = 1, -1.0
-    b = rewl.Batch([run_kwargs(p) for p in params], walkers_per_wave=1)
-    for P in candidates:
-        try:
-            b.set_walkers_per_wave(P)
-        except rewl.RewlError:
-            continue
-        b.step(1)
-        torch.cuda.synchronize()
-        a0 = sum(b[i].info()["attempts"] for i in range(len(params)))
-        t0 = time.perf_counter()
-        b.step(rounds)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        rate = (sum(b[i].info()["attempts"] for i in range(len(params))) - a0) / dt
-        log(f"autotune: walkers per wave {P}: {rate / 1e9:.3f} G attempts/s")
-        if rate > best_rate:
-            best, best_rate = P, rate
-    b.close()
-    return best
-
-
-def cpu_baseline(p, seconds, finish, threads):
-    """The oracle on the same workload with `threads` OpenMP threads over its
-    first rounds (all windows active); the time-to-DOS follows from its
-    per-walker round time and the static schedule over the GPU run's rounds."""
-    from oracle import core
-
-    o = core.Run(**run_kwargs(p), n_threads=threads)
-    a0 = o.stats()["attempts"]
-    t0 = time.perf_counter()
-    rounds = 0
-    while True:
-        o.step(1)
-        rounds += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or o.info()["done"]:
-            break
-    att = o.stats()["attempts"] - a0
-    nw = p["n_windows"] * p["walkers_per_window"]
-    m = p["walkers_per_window"]
-    chunk = math.ceil(nw / threads)                   # walkers per thread, static schedule
-    per_walker_round = el / rounds / chunk            # one walker's S attempts on one thread
-    total = 0.0
-    edges = sorted(set([0] + [f + 1 for f in finish]))
-    for r0, r1 in zip(edges, edges[1:]):
-        per_thread = [0] * threads
-        for w in range(nw):
-            if finish[w // m] >= r0:
-                per_thread[w // chunk] += 1
-        total += (r1 - r0) * max(per_thread) * per_walker_round
-    return {"value": att / el, "unit": "attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{p['name']} seed {p['seed']}: first {rounds} rounds after start-up "
-                      f"({att} sweep attempts in {el:.1f} s, OpenMP static over {nw} walkers)",
-            "time_to_dos_s_extrapolated": total}
-
-
 def profile(rewl, args, run_params):
     """Fixed rounds of one run (or of a batch) after start-up, for profilers."""
     import torch
@@ -330,8 +269,9 @@ def profile(rewl, args, run_params):
         runs = [run_kwargs(run_params(args.workload, seed=1 + i, **over))
                 for i in range(args.batch)]
         P = args.walkers_per_wave
-        r = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0)
-        label = f"{len(runs)} x {args.workload}, P={P}"
+        r = rewl.Batch(runs, walkers_per_wave=P, graph_rounds=0,
+                       form=args.form if args.form != "auto" else "rounds")
+        label = f"{len(runs)} x {args.workload}, P={P}, {args.form}"
         views = [r[i] for i in range(len(runs))]
     else:
         r = rewl.Run(**run_kwargs(run_params(args.workload, seed=1, **over)))
@@ -529,7 +469,8 @@ def errors(rewl, args):
 
 def calibrate_copy(mb):
     """One device-to-device copy of `mb` MiB (read mb, write mb) for scaling
-    the FETCH_SIZE / WRITE_SIZE counters."""
+    the FETCH_SIZE / WRITE_SIZE counters; use a copy several times larger than
+    the 256 MB last-level cache so that its reads come from HBM."""
     import torch
 
     src = torch.ones(mb << 18, dtype=torch.float32, device="cuda")
@@ -540,25 +481,165 @@ def calibrate_copy(mb):
     log(f"copy: {mb} MiB read, {mb} MiB written")
 
 
+
+def plain_rate(rewl, name, rounds):
+    """One plain run of a workload: attempts/s and the sweep kernel's average
+    launch over `rounds` rounds right after start-up (every window running)."""
+    import torch
+
+    from workloads import run_params
+
+    r = rewl.Run(**run_kwargs(run_params(name, seed=1)))
+    r.set_timing(True)
+    r.step(1)
+    torch.cuda.synchronize()
+    a0 = r.info()["attempts"]
+    ms0, n0 = r.timing()
+    t0 = time.perf_counter()
+    r.step(rounds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = r.timing()
+    att = r.info()["attempts"] - a0
+    r.close()
+    return {"workload": WORKLOAD_TEXT[name], "rounds": rounds, "attempts_per_s": att / wall,
+            "sweep_avg_us": 1e3 * (ms - ms0) / max(n - n0, 1)}
+
+
+def time_to_dos_small(rewl, seeds, budget_plain_s):
+    """p50/p99 time-to-converged ln g of the 8x8 Ising workload: each seed as a
+    plain run, one after another (time from creation to the stitched ln g on
+    the host), and all seeds in one batch, launched as the autotuner picks and
+    polled every 16 rounds (time from the batch's creation to the run's
+    stitched ln g on the host)."""
+    import numpy as np
+    import torch
+
+    from paper_1305_5615_amd import autotune
+    from workloads import run_params
+
+    params = [run_params("ising8", seed=s) for s in seeds]
+    plain, plain_err, plain_att = [], [], 0
+    t_start = time.perf_counter()
+    for p in params:
+        if time.perf_counter() - t_start > budget_plain_s:
+            log(f"time-to-DOS: plain runs stopped after {len(plain)} seeds (budget)")
+            break
+        res = gpu_full_run(rewl, p, 100_000)
+        plain.append(res["seconds"])
+        plain_att += res["attempts"]
+        plain_err.append(exact_error(p, res["lng"]))
+    kws = [run_kwargs(p) for p in params]
+    setting, _, _ = autotune.tune(kws, P_options=(1, 2, 8), forms=("rounds", "persistent"),
+                                  graph_options=(0, 16), rounds=8, log=log)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = rewl.Batch(kws, walkers_per_wave=setting.walkers_per_wave,
+                   graph_rounds=setting.graph_rounds, form=setting.form)
+    done_at = [None] * len(params)
+    errs = [None] * len(params)
+    issued = 0
+    while issued < 100_000:
+        b.step(16)
+        issued += 16
+        d = b.done()
+        for i in np.nonzero(d)[0]:
+            if done_at[i] is None:
+                lng = b[int(i)].lng()
+                done_at[i] = time.perf_counter() - t0
+                errs[i] = exact_error(params[i], lng)
+        if d.all():
+            break
+    wall = time.perf_counter() - t0
+    att = attempts_of([b[i] for i in range(len(params))])
+    b.close()
+    got = [x for x in done_at if x is not None]
+    # the same requests all arriving at once and served one after another:
+    # a run's time-to-DOS then includes waiting for the runs before it
+    fifo = list(np.cumsum(plain))
+    return {"workload": WORKLOAD_TEXT["ising8"], "seeds": [int(s) for s in seeds],
+            "plain_fifo": {"runs": len(fifo), "p50_s": percentile(fifo, 50),
+                           "p99_s": percentile(fifo, 99)},
+            "plain": {"runs": len(plain), "p50_s": percentile(plain, 50),
+                      "p99_s": percentile(plain, 99), "wall_s": sum(plain),
+                      "attempts_per_s": plain_att / sum(plain) if plain else None,
+                      "max_abs_dlng_vs_exact": plain_err},
+            "batched": {"runs": len(got), "p50_s": percentile(got, 50),
+                        "p99_s": percentile(got, 99), "wall_s": wall,
+                        "attempts_per_s": att / wall, "setting": setting._asdict(),
+                        "max_abs_dlng_vs_exact": errs}}
+
+
+def oracle_rate(params, threads, seconds, max_rounds=10**9):
+    """The oracle's sweep attempts per second on `params` (one run after
+    another, start-up untimed), stepping rounds until `seconds` have passed or
+    the run has converged."""
+    from oracle import core
+
+    att, el, rounds = 0, 0.0, 0
+    for p in params:
+        o = core.Run(**run_kwargs(p), n_threads=threads)
+        a0 = o.stats()["attempts"]
+        t0 = time.perf_counter()
+        r = 0
+        while r < max_rounds and not o.info()["done"]:
+            o.step(1)
+            r += 1
+            if time.perf_counter() - t0 >= seconds / len(params):
+                break
+        el += time.perf_counter() - t0
+        att += o.stats()["attempts"] - a0
+        rounds += r
+    return att / el, rounds, att, el
+
+
+def cpu_baseline(threads, seconds):
+    """The oracle on the headline workload (two of the 256 instances, a few
+    rounds each, all host threads), plus single-core and all-core rates on
+    every workload."""
+    from workloads import run_params
+
+    glass = [run_params("ea24", seed=s) for s in (1, 2)]
+    v, rounds, att, el = oracle_rate(glass, threads, seconds)
+    out = {"value": v, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+           "sample": f"instances 1-2 of the 256 24x24 +-J glasses, {rounds} rounds after "
+                     f"start-up ({att} sweep attempts in {el:.1f} s), OpenMP over each "
+                     f"instance's 32 walkers, {threads} threads",
+           "per_workload": {}}
+    for name in ("ising8", "ising32", "potts64", "ea24"):
+        p = [run_params(name, seed=1)]
+        rec = {}
+        for label, th in (("one_core", 1), ("all_cores", threads)):
+            r, n, a, e = oracle_rate(p, th, seconds / 4)
+            rec[label] = {"attempts_per_s": r, "rounds": n, "threads": th}
+        out["per_workload"][name] = rec
+        log(f"cpu: {name}: 1 core {rec['one_core']['attempts_per_s']:.3g}, "
+            f"{threads} threads {rec['all_cores']['attempts_per_s']:.3g} attempts/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="ising32", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--max-rounds", type=int, default=400000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch", type=int, default=16,
-                    help="runs in the batched comparison (0: skip); in profile mode with "
-                         "--walkers-per-wave, the batch size")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--form", default="auto", choices=("auto", "rounds", "persistent"),
+                    help="launch form of the headline batch (auto: the autotuner's choice)")
     ap.add_argument("--walkers-per-wave", type=int, default=0,
-                    help="batched form: walkers per wave (0: autotune)")
-    ap.add_argument("--graph", type=int, default=16, help="batched form: rounds per graph")
-    ap.add_argument("--glasses", type=int, default=256,
-                    help="batched glass leg: independent 24x24 +-J runs in one batch (0: skip)")
-    ap.add_argument("--glass-rounds", type=int, default=100,
-                    help="batched glass leg: rounds timed after start-up")
+                    help="walkers per wave of the headline batch (0: autotune); in profile "
+                         "mode with --batch, the batch's setting")
+    ap.add_argument("--legs", default="all", choices=("all", "headline"),
+                    help="headline only, or the bounded sub-measurements too")
+    ap.add_argument("--budget", type=float, default=150.0,
+                    help="wall-clock seconds for the optional legs and the CPU baseline")
+    ap.add_argument("--glasses", type=int, default=256, help="runs in the headline batch")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="ising32", choices=sorted(WORKLOAD_TEXT),
+                    help="profile / balanced / errors modes: the workload")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="profile mode: this many runs of the workload in one batch")
+    ap.add_argument("--max-rounds", type=int, default=400000)
     ap.add_argument("--rounds", type=int, default=0,
                     help="profile mode: run this many rounds after start-up, then exit")
     ap.add_argument("--attempts-per-round", type=int, default=0,
@@ -590,6 +671,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     import paper_1305_5615_amd as rewl
+    from paper_1305_5615_amd import autotune
     from workloads import run_params
 
     if args.rounds > 0:
@@ -608,101 +690,73 @@ def main():
         errors(rewl, args)
         return
 
-    base = dict(run_params(args.workload, seed=1))
-    model = base["model"]
-    for i in range(args.warmup):
-        res = gpu_full_run(rewl, run_params(args.workload, seed=900 + i), args.max_rounds)
-        log(f"warmup {i}: {res['seconds']:.2f} s, {res['rounds']} rounds")
-
-    runs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        res = gpu_full_run(rewl, run_params(args.workload, seed=1 + i), args.max_rounds)
-        if not res["converged"]:
-            log(f"step {i}: not converged within {args.max_rounds} rounds")
-        runs.append(res)
-        log(f"step {i}: {res['seconds']:.2f} s, {res['rounds']} rounds, "
-            f"{res['attempts'] / res['seconds'] / 1e9:.3f} G attempts/s")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    attempts = sum(r["attempts"] for r in runs)
-    sweep_ms = sum(r["sweep_ms"] for r in runs)
-    launches = sum(r["launches"] for r in runs)
-    times = [r["seconds"] for r in runs]
-
-    slots = VALU_SLOTS_PER_ATTEMPT[model]
-    achieved = slots * attempts / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS if achieved else None,
-                "traffic": profiled_traffic(args.workload),
-                "kernel": sweep_kernel_name(1, base["n_windows"] * base["walkers_per_window"]),
-                "sweep_avg_us": 1e3 * sweep_ms / launches if launches else None,
-                "valu_slots_per_attempt": slots}
+    budget = Budget(args.budget)
+    runs = glass_runs(args.glasses)
+    # the launch setting: walkers per wave (8 or 4 fill the chip's SIMDs with
+    # 8192 walkers) and the form; graphs are left out because the timed region
+    # records HIP events around every launch
+    forms = ("rounds", "persistent") if args.form == "auto" else (args.form,)
+    Ps = (args.walkers_per_wave,) if args.walkers_per_wave else (4, 8)
+    if len(forms) * len(Ps) > 1:
+        setting, rate, table = autotune.tune(runs, P_options=Ps, forms=forms, graph_options=(0,),
+                                             rounds=2, log=log)
+        tuned = [{"setting": c._asdict(), "attempts_per_s": r} for c, r in table]
+    else:
+        setting = autotune.Setting(Ps[0], forms[0], 0, None)
+        tuned = []
+    log(f"headline: {setting}")
+    res = timed_batch(rewl, runs, setting, args.steps, args.warmup)
+    waves = len(runs) * 32 // setting.walkers_per_wave
+    kname = kernel_name(rewl, setting.form, setting.walkers_per_wave, waves)
+    tag = f"{'persist' if setting.form == 'persistent' else 'sweep'}_ea24x256_P{setting.walkers_per_wave}"
+    value = res["attempts"] / res["wall"]
+    log(f"headline: {args.steps} rounds, {res['attempts']} attempts in {res['wall']:.4f} s = "
+        f"{value / 1e9:.2f} G attempts/s; {res['launches']} launches, "
+        f"{res['launch_ms']:.3f} ms")
     out = {
         "metric": "spin-flip attempts/sec (1 GPU) + p50/p99 time-to-converged ln g, "
                   "batched vs plain",
-        "value": attempts / wall, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * res["wall"] / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload], "form": "plain",
-                   "walkers": base["n_windows"] * base["walkers_per_window"],
-                   "L": base["L"], "q": base["q"], "seeds": list(range(1, args.steps + 1))},
-        "time_to_dos_s": {"p50": percentile(times, 50), "p99": percentile(times, 99),
-                          "rounds": [r["rounds"] for r in runs]},
-        "max_abs_dlng_vs_exact": [exact_error(base, r["lng"]) for r in runs],
-        "roofline": roofline,
+        "config": {"workload": HEADLINE, "form": setting.form,
+                   "walkers_per_wave": setting.walkers_per_wave, "runs": len(runs),
+                   "walkers": len(runs) * 32, "attempts_per_step": res["attempts"] / args.steps},
+        "roofline": roofline(res["attempts"], res["launches"], res["launch_ms"],
+                             profiled_traffic(tag), kname),
+        "autotune": tuned,
     }
-    if args.batch > 0:
-        params = [run_params(args.workload, seed=1 + i) for i in range(args.batch)]
-        P = args.walkers_per_wave or autotune(rewl, params)
-        bres = gpu_batched(rewl, params, P, args.graph, args.max_rounds)
-        dts = [d for d in bres["done_at"] if d is not None]
-        out["batched"] = {"runs": args.batch, "walkers_per_wave": P, "graph_rounds": args.graph,
-                          "value": bres["attempts"] / bres["wall"], "unit": "attempts/s",
-                          "wall_s": bres["wall"], "converged": len(dts),
-                          "time_to_dos_s": {"p50": percentile(dts, 50),
-                                            "p99": percentile(dts, 99)},
-                          "seeds": list(range(1, args.batch + 1))}
-        import numpy as np
-
-        done_lng = [x for x in bres["lng"] if x is not None]
-        errs = [exact_error(params[i], x) for i, x in enumerate(bres["lng"]) if x is not None]
-        if len(done_lng) >= 2 and all(e is not None for e in errs):
-            # independent runs: the mean ln g and its jackknife error bar
-            mean, jk = rewl.jackknife(np.array(done_lng))
-            fin = np.isfinite(mean)
-            out["batched"]["max_abs_dlng_vs_exact"] = {
-                "per_run": errs, "mean_of_runs": exact_error(params[0], mean),
-                "max_jackknife_error_of_mean": float(np.nanmax(jk[fin]))}
-        log(f"batched: {args.batch} runs, P={P}, {bres['wall']:.1f} s, "
-            f"{bres['attempts'] / bres['wall'] / 1e9:.3f} G attempts/s")
-    if args.glasses > 0:
-        g = gpu_glasses(rewl, args.glasses, args.glass_rounds)
-        ach = VALU_SLOTS_PER_ATTEMPT["ea"] * g["attempts"] / (g["sweep_ms"] * 1e-3) / 1e12
-        out["batched_glasses"] = {
-            "workload": f"{args.glasses} independent 2D +-J EA glasses L=24, 8 windows x 4 "
-                        f"walkers each, {args.glass_rounds * 10_000} attempts/walker timed, "
-                        "one batch",
-            "walkers_per_wave": g["P"], "attempts_per_round": g["S"],
-            "value": g["attempts"] / g["wall"],
-            "unit": "attempts/s",
-            "roofline": {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
-                         "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
-                         # state in and out once per launch: the same bytes at any S
-                         "traffic": profiled_traffic(f"ea24x{args.glasses}_P{g['P']}"),
-                         "kernel": sweep_kernel_name(g["P"], args.glasses * 32 // g["P"]),
-                         "sweep_avg_us": 1e3 * g["sweep_ms"] / max(g["launches"], 1),
-                         "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT["ea"]}}
-        log(f"glasses: {args.glasses} runs, P={g['P']}, S={g['S']}, "
-            f"{g['attempts'] / g['wall'] / 1e9:.2f} G attempts/s")
-    if not args.no_cpu:
-        p = dict(run_params(args.workload, seed=1))
-        p["name"] = args.workload
+    legs = {}
+    if args.legs == "all":
+        other = "rounds" if setting.form == "persistent" else "persistent"
+        if budget.allows(10, "other form"):
+            try:
+                o = timed_batch(rewl, runs, setting._replace(form=other), args.steps, args.warmup)
+                legs["other_form"] = {
+                    "form": other, "walkers_per_wave": setting.walkers_per_wave,
+                    "attempts_per_s": o["attempts"] / o["wall"],
+                    "launch_avg_us": 1e3 * o["launch_ms"] / max(o["launches"], 1),
+                    "launches": o["launches"]}
+            except rewl.RewlError as e:
+                legs["other_form"] = {"form": other, "error": str(e)}
+        for name, rounds in (("ising32", 300), ("potts64", 60)):
+            if budget.allows(15, name):
+                legs[f"plain_{name}"] = plain_rate(rewl, name, rounds)
+                log(f"plain {name}: {legs[f'plain_{name}']['attempts_per_s'] / 1e9:.3f} G/s")
+        if budget.allows(45, "time-to-DOS"):
+            legs["time_to_dos_ising8"] = time_to_dos_small(rewl, range(1, 21),
+                                                          min(30.0, budget.left() - 15))
+            t = legs["time_to_dos_ising8"]
+            log(f"time-to-DOS 8x8 Ising: plain alone p50 {t['plain']['p50_s']:.3f} s p99 "
+                f"{t['plain']['p99_s']:.3f} s; plain one after another p50 "
+                f"{t['plain_fifo']['p50_s']:.2f} s p99 {t['plain_fifo']['p99_s']:.2f} s; "
+                f"batched p50 {t['batched']['p50_s']:.3f} s p99 {t['batched']['p99_s']:.3f} s")
+    out["legs"] = legs
+    if not args.no_cpu and budget.allows(args.cpu_seconds * 2 + 5, "cpu baseline"):
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else \
             (os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, runs[0]["finish"], threads)
+        out["cpu_baseline"] = cpu_baseline(threads, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

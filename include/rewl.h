@@ -258,6 +258,22 @@ int rewl_batch_create(rewl_batch **out, const rewl_params *runs, int n_runs,
                       int walkers_per_wave, void *hip_stream);
 int rewl_batch_get_run(rewl_batch *b, int i, rewl_ctx **run);
 int rewl_batch_set_walkers_per_wave(rewl_batch *b, int walkers_per_wave);
+/* How rounds are launched (results never depend on it):
+ *  REWL_FORM_ROUNDS (default): every round is one launch of each kernel over
+ *    all runs (sweep, flatness/merge, exchange, round counters); the walkers'
+ *    state goes through device memory between them;
+ *  REWL_FORM_PERSISTENT: one launch per call of rewl_batch_step (cut into
+ *    launches of at most 1024 rounds) in which one work-group holds one run,
+ *    loads its walkers' state into LDS once and loops the rounds -- sweep,
+ *    flatness, merges and the exchange step (Eq. (1)) as work-group steps
+ *    between barriers -- then writes it back; the h x m hierarchy of the
+ *    parallel-scheme paragraph held by one CU.  A work-group finishes early
+ *    once every window of its run is done.  Requires every run to fit one
+ *    work-group: at most 64 walkers, at most 8 waves of walkers_per_wave
+ *    walkers, and their LDS within one CU (160 KiB); REWL_EINVAL otherwise,
+ *    and the form is left unchanged.  Graphs are not used in this form. */
+enum { REWL_FORM_ROUNDS = 0, REWL_FORM_PERSISTENT = 1 };
+int rewl_batch_set_form(rewl_batch *b, int form);
 /* rounds_per_graph > 0: rounds are issued as replays of a captured HIP graph of
  * that many rounds (remaining rounds as direct launches); 0: direct launches.
  * Graphs are not used while timing is on. */

@@ -81,6 +81,7 @@ def lib():
         L.rewl_batch_get_run.argtypes = [P, i32, C.POINTER(P)]
         L.rewl_batch_set_walkers_per_wave.argtypes = [P, i32]
         L.rewl_batch_set_graph.argtypes = [P, i32]
+        L.rewl_batch_set_form.argtypes = [P, i32]
         L.rewl_batch_step.argtypes = [P, i64]
         L.rewl_batch_run.argtypes = [P, i64, C.POINTER(i64)]
         L.rewl_batch_done.argtypes = [P, P, i32]
@@ -352,17 +353,34 @@ class Run(RunView):
         return self
 
 
+FORMS = {"rounds": 0, "persistent": 1}
+
+
 class Batch:
     """Many independent runs advanced together (see rewl_batch_create).
 
     runs: list of keyword dicts as for Run (model, L, q, couplings, ...).
+    walkers_per_wave: 1, 2, 4 or 8; 0 lets the autotuner (autotune.tune) pick
+    walkers per wave, the form and the rounds per graph for this shape of
+    batch (the choice is cached per shape; results never depend on it).
+    form: "rounds" (kernel launches per round, graph_rounds > 0 replays a
+    captured graph of that many rounds) or "persistent" (one work-group per run
+    loops the rounds with the run in LDS).
     """
 
-    def __init__(self, runs, walkers_per_wave=1, graph_rounds=0, stream=None):
+    def __init__(self, runs, walkers_per_wave=1, graph_rounds=0, stream=None, form="rounds"):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        self.setting = None
+        if walkers_per_wave == 0:
+            from .autotune import tune
+
+            self.setting = tune(runs)[0]
+            walkers_per_wave = self.setting.walkers_per_wave
+            graph_rounds = self.setting.graph_rounds
+            form = self.setting.form
         self._keep = []
         arr = (Params * len(runs))()
         for i, kw in enumerate(runs):
@@ -385,6 +403,12 @@ class Batch:
             self._views.append(v)
         if graph_rounds:
             self.set_graph(graph_rounds)
+        if form != "rounds":
+            try:
+                self.set_form(form)
+            except RewlError:
+                self.close()
+                raise
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -411,6 +435,10 @@ class Batch:
     def set_graph(self, rounds):
         _check(lib().rewl_batch_set_graph(self._h, int(rounds)), "rewl_batch_set_graph")
 
+    def set_form(self, form):
+        """"rounds" or "persistent" (rewl_batch_set_form)."""
+        _check(lib().rewl_batch_set_form(self._h, FORMS[form]), "rewl_batch_set_form")
+
     def step(self, rounds):
         _check(lib().rewl_batch_step(self._h, int(rounds)), "rewl_batch_step")
 
@@ -434,14 +462,26 @@ class Batch:
 
 
 class Server:
-    """Continuous batching of arriving runs (see rewl_server_create)."""
+    """Continuous batching of arriving runs (see rewl_server_create).
+
+    walkers_per_wave=0 lets the autotuner pick it from `sample`, a list of run
+    keyword dicts shaped like the expected requests (timed as one batch in
+    the per-round form the server uses; cached per shape)."""
 
     def __init__(self, device_budget_bytes=8 << 30, walkers_per_wave=1, rounds_per_tick=8,
-                 stream=None):
+                 stream=None, sample=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the REWL library runs on the GPU only")
+        self.setting = None
+        if walkers_per_wave == 0:
+            if not sample:
+                raise ValueError("walkers_per_wave=0 needs a sample of requests to tune on")
+            from .autotune import tune
+
+            self.setting = tune(sample, forms=("rounds",), graph_options=(0,))[0]
+            walkers_per_wave = self.setting.walkers_per_wave
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         _check(lib().rewl_server_create(C.byref(h), int(device_budget_bytes),

@@ -20,17 +20,22 @@
 
 namespace {
 
-thread_local std::string g_err;
+// the calling thread's last error message (a fixed buffer: setting it never
+// allocates)
+thread_local char g_err[512];
 
-int fail(int code, const std::string &msg)
+int fail(int code, const char *msg)
 {
-    g_err = msg;
+    std::snprintf(g_err, sizeof g_err, "%s", msg);
     return code;
 }
 
+int fail(int code, const std::string &msg) { return fail(code, msg.c_str()); }
+
 int hip_fail(hipError_t e, const char *what)
 {
-    return fail(REWL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    std::snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+    return REWL_EDEVICE;
 }
 
 #define HIP_TRY(call)                                  \
@@ -40,6 +45,9 @@ int hip_fail(hipError_t e, const char *what)
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// most rounds one persistent launch loops (a longer request is several launches)
+constexpr int64_t kPersistChunk = 1024;
 
 // bonds per site: 2 on the square lattice, 3 on the cubic one
 int bonds_per_site(int model) { return model == REWL_EA3 ? 3 : 2; }
@@ -55,10 +63,8 @@ struct Geometry {
 // Windows: span = B-1, w = span / (1 + (h-1)(1-o)); lo_k = floor(k (1-o) w),
 // hi_k = min(B-1, ceil(k (1-o) w + w)), hi_{h-1} = B-1 ("equal-size intervals
 // with overlap o", Fig. 1a caption), evaluated in this order in binary64.
-int make_windows(int64_t B, int h, double o, std::vector<int64_t> &lo, std::vector<int64_t> &hi)
+int make_windows(int64_t B, int h, double o, int64_t *lo, int64_t *hi)
 {
-    lo.assign(h, 0);
-    hi.assign(h, 0);
     const double span = (double)(B - 1);
     const double w = span / (1.0 + (double)(h - 1) * (1.0 - o));
     for (int k = 0; k < h; ++k) {
@@ -81,7 +87,7 @@ int make_windows(int64_t B, int h, double o, std::vector<int64_t> &lo, std::vect
 
 // An explicit partition: n windows from bin 0 to bin B-1, starts and ends
 // increasing, >= 2 bins each, >= 2 bins shared by neighbours.
-int check_windows(int64_t B, int n, const std::vector<int64_t> &lo, const std::vector<int64_t> &hi)
+int check_windows(int64_t B, int n, const int64_t *lo, const int64_t *hi)
 {
     if (n < 1 || lo[0] != 0 || hi[n - 1] != B - 1)
         return fail(REWL_EINVAL, "windows must run from the first to the last bin");
@@ -98,7 +104,9 @@ int check_windows(int64_t B, int n, const std::vector<int64_t> &lo, const std::v
     return REWL_OK;
 }
 
-int validate(const rewl_params *p, Geometry &g)
+// Checks the parameters and derives the geometry; the windows (n_windows
+// first and last bins) go to lo / hi, which hold n_windows entries.
+int validate_into(const rewl_params *p, Geometry &g, int64_t *lo, int64_t *hi)
 {
     if (!p) return fail(REWL_EINVAL, "params is NULL");
     if (p->model < 0 || p->model > 3) return fail(REWL_EINVAL, "unknown model");
@@ -152,21 +160,37 @@ int validate(const rewl_params *p, Geometry &g)
     if (p->window_lo || p->window_hi) {
         if (!p->window_lo || !p->window_hi)
             return fail(REWL_EINVAL, "window_lo and window_hi go together");
-        g.lo.assign(p->window_lo, p->window_lo + p->n_windows);
-        g.hi.assign(p->window_hi, p->window_hi + p->n_windows);
-        rc = check_windows(g.B, p->n_windows, g.lo, g.hi);
+        for (int k = 0; k < p->n_windows; ++k) {
+            lo[k] = p->window_lo[k];
+            hi[k] = p->window_hi[k];
+        }
+        rc = check_windows(g.B, p->n_windows, lo, hi);
     } else {
-        rc = make_windows(g.B, p->n_windows, p->overlap, g.lo, g.hi);
+        rc = make_windows(g.B, p->n_windows, p->overlap, lo, hi);
     }
     if (rc) return rc;
     g.Wmax = 0;
     for (int k = 0; k < p->n_windows; ++k)
-        g.Wmax = std::max<int>(g.Wmax, (int)(g.hi[k] - g.lo[k] + 1));
+        g.Wmax = std::max<int>(g.Wmax, (int)(hi[k] - lo[k] + 1));
     g.nw = p->n_windows * p->walkers_per_window;
     g.Npad = (int)align_up((size_t)N, 16);
     if (sweep_lds_bytes(1, g.Wmax, g.N, model_j_words(p->model)) > kMaxLds)
         return fail(REWL_EINVAL, "one walker's window does not fit the LDS of a CU");
     return REWL_OK;
+}
+
+// most windows of a run (every window has >= 2 bins and the widest lattice has
+// 2^17 + 1 bins, so more are never valid)
+constexpr int kMaxWindows = 1 << 17;
+
+int validate(const rewl_params *p, Geometry &g)
+{
+    if (!p) return fail(REWL_EINVAL, "params is NULL");
+    if (p->n_windows < 1) return fail(REWL_EINVAL, "n_windows must be >= 1");
+    if (p->n_windows > kMaxWindows) return fail(REWL_EINVAL, "too many windows");
+    g.lo.assign(p->n_windows, 0);
+    g.hi.assign(p->n_windows, 0);
+    return validate_into(p, g, g.lo.data(), g.hi.data());
 }
 
 // Byte offsets of the arrays inside the device allocation.
@@ -246,6 +270,7 @@ struct rewl_batch {
     std::vector<hipEvent_t> ev_free, ev_pending;
     double sweep_ms = 0.0;
     int64_t sweep_launches = 0;
+    int form = REWL_FORM_ROUNDS;   // REWL_FORM_ROUNDS or REWL_FORM_PERSISTENT
     int graph_rounds = 0;          // > 0: replay a captured graph of this many rounds
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
@@ -343,6 +368,22 @@ int rebuild(rewl_batch *b)
     }
     if (sweep_lds_bytes(b->P, max_W, max_N, j_words) > kMaxLds)
         return fail(REWL_EINVAL, "walkers_per_wave too large for these runs' LDS footprint");
+    int pwaves = 0;
+    if (b->form == REWL_FORM_PERSISTENT) {
+        // every run in one work-group: its waves of P walkers and their LDS
+        for (rewl_ctx *r : b->runs) {
+            if (!r) continue;
+            if (r->g.nw > kPersistMaxWalkers)
+                return fail(REWL_EINVAL, "persistent form: a run has more than 64 walkers");
+            pwaves = std::max(pwaves, (r->g.nw + b->P - 1) / b->P);
+        }
+        if (pwaves > kPersistMaxWaves)
+            return fail(REWL_EINVAL, "persistent form: a run needs more than 8 waves at this "
+                                     "walkers_per_wave");
+        if (persist_lds_bytes(b->P, pwaves, max_W, max_N, j_words) > kPersistMaxDynLds)
+            return fail(REWL_EINVAL, "persistent form: a run does not fit the LDS of one CU at "
+                                     "this walkers_per_wave");
+    }
     const size_t n_runs = descs.size();
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -383,6 +424,7 @@ int rebuild(rewl_batch *b)
     d.max_W = max_W;
     d.j_words = j_words;
     d.region = (int)sweep_region(max_W, max_N, kWave / b->P);
+    d.pwaves = pwaves;
     b->done_d = (int *)(t + o_done);
     if (b->pinned_cap < std::max<size_t>(n_runs, 1)) {
         if (b->pinned) (void)hipHostFree(b->pinned);
@@ -405,7 +447,9 @@ int launch_rounds(rewl_batch *b, int64_t rounds)
             if (rc) return rc;
         }
         const int rc = rewl_launch_round(b->dev, b->stream, e0, e1);
-        if (rc) return fail(rc == -1 ? REWL_EINVAL : REWL_EDEVICE, "kernel launch failed");
+        if (rc)
+            return fail(rc == -1 ? REWL_EINVAL : REWL_EDEVICE,
+                        std::string("kernel launch failed: ") + rewl_launch_error());
         b->rounds += 1;
     }
     return REWL_OK;
@@ -419,6 +463,26 @@ int batch_step(rewl_batch *b, int64_t rounds)
         if (rc) return rc;
     }
     if (b->dev.n_runs == 0) return REWL_OK;
+    if (b->form == REWL_FORM_PERSISTENT) {
+        // one launch loops the rounds; long requests are cut into launches of
+        // at most kPersistChunk rounds (the state passes through HBM between)
+        while (rounds > 0) {
+            const int64_t n = std::min<int64_t>(rounds, kPersistChunk);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (b->timing) {
+                int rc = take_event(b, &e0);
+                if (!rc) rc = take_event(b, &e1);
+                if (rc) return rc;
+            }
+            const int rc = rewl_launch_persist(b->dev, (long long)n, b->stream, e0, e1);
+            if (rc)
+                return fail(rc == -1 ? REWL_EINVAL : REWL_EDEVICE,
+                            std::string("persistent launch failed: ") + rewl_launch_error());
+            b->rounds += n;
+            rounds -= n;
+        }
+        return REWL_OK;
+    }
     const int R = b->graph_rounds;
     if (R > 0 && !b->timing) {
         if (!b->graph) {
@@ -519,6 +583,30 @@ void free_batch(rewl_batch *b)
     delete b;
 }
 
+// The scalar fields of a run's descriptor (the array pointers are the caller's).
+void fill_desc(RunDesc &d, const rewl_params *p, const Geometry &g)
+{
+    d.model = p->model;
+    d.L = p->L;
+    d.N = g.N;
+    d.q = (p->model == REWL_POTTS) ? p->q : 2;
+    d.h = p->n_windows;
+    d.m = p->walkers_per_window;
+    d.nw = g.nw;
+    d.Npad = g.Npad;
+    d.Wmax = g.Wmax;
+    d.e_min = (int)g.e_min;
+    d.step = g.step;
+    d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
+    d.l2_magic = (uint32_t)(((uint64_t)1 << 32) / ((uint64_t)p->L * (uint64_t)p->L) + 1);
+    d.key0 = (uint32_t)p->seed;
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.S = p->attempts_per_round;
+    d.schedule = p->schedule;
+    d.flat_p = p->flatness;
+    d.lnf_final = p->lnf_final;
+}
+
 // Make one run: validate, lay out, allocate (or adopt) its slab, upload its
 // parameters and run the start-up kernel on `stream`.
 int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t buffer_bytes,
@@ -558,25 +646,7 @@ int make_run(rewl_ctx **out, const rewl_params *p, void *device_buffer, size_t b
     }
     char *b = (char *)h->base;
     RunDesc &d = h->desc;
-    d.model = p->model;
-    d.L = p->L;
-    d.N = g.N;
-    d.q = (p->model == REWL_POTTS) ? p->q : 2;
-    d.h = p->n_windows;
-    d.m = p->walkers_per_window;
-    d.nw = g.nw;
-    d.Npad = g.Npad;
-    d.Wmax = g.Wmax;
-    d.e_min = (int)g.e_min;
-    d.step = g.step;
-    d.l_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)p->L + 1);
-    d.l2_magic = (uint32_t)(((uint64_t)1 << 32) / ((uint64_t)p->L * (uint64_t)p->L) + 1);
-    d.key0 = (uint32_t)p->seed;
-    d.key1 = (uint32_t)(p->seed >> 32);
-    d.S = p->attempts_per_round;
-    d.schedule = p->schedule;
-    d.flat_p = p->flatness;
-    d.lnf_final = p->lnf_final;
+    fill_desc(d, p, g);
     d.spins = (int8_t *)(b + h->l.spins);
     d.E = (int *)(b + h->l.E);
     d.t = (unsigned long long *)(b + h->l.t);
@@ -748,7 +818,7 @@ int stitch(const rewl_ctx *h, const std::vector<double> &P, double *out)
 
 extern "C" {
 
-const char *rewl_last_error(void) { return g_err.c_str(); }
+const char *rewl_last_error(void) { return g_err; }
 
 int rewl_footprint(const rewl_params *p, size_t *device_bytes, size_t *lds_bytes)
 {
@@ -1134,7 +1204,7 @@ int rewl_partition_balanced(int64_t n_bins, int n_windows, double overlap, int p
         !pre_lo || !pre_hi || !first_rounds || !lo || !hi)
         return fail(REWL_EINVAL, "bad arguments");
     const std::vector<int64_t> plo(pre_lo, pre_lo + pre_windows), phi(pre_hi, pre_hi + pre_windows);
-    if (check_windows(n_bins, pre_windows, plo, phi)) return REWL_EINVAL;
+    if (check_windows(n_bins, pre_windows, plo.data(), phi.data())) return REWL_EINVAL;
     for (int k = 0; k < pre_windows; ++k)
         if (first_rounds[k] < 1) return fail(REWL_EINVAL, "first-iteration rounds must be >= 1");
     // time density of each bin in the first iteration: the pre-run windows
@@ -1169,7 +1239,7 @@ int rewl_partition_balanced(int64_t n_bins, int n_windows, double overlap, int p
         H[(size_t)k] = last;
     }
     H[(size_t)n_windows - 1] = n_bins - 1;
-    if (check_windows(n_bins, n_windows, L, H)) return REWL_EINVAL;
+    if (check_windows(n_bins, n_windows, L.data(), H.data())) return REWL_EINVAL;
     for (int k = 0; k < n_windows; ++k) {
         lo[k] = L[(size_t)k];
         hi[k] = H[(size_t)k];
@@ -1340,6 +1410,26 @@ int rewl_batch_set_walkers_per_wave(rewl_batch *b, int walkers_per_wave)
     return rc;
 }
 
+int rewl_batch_set_form(rewl_batch *b, int form)
+{
+    if (!b || (form != REWL_FORM_ROUNDS && form != REWL_FORM_PERSISTENT))
+        return fail(REWL_EINVAL, "form must be REWL_FORM_ROUNDS or REWL_FORM_PERSISTENT");
+    int rc = bsync(b);
+    if (rc) return rc;
+    const int old = b->form;
+    b->form = form;
+    b->dirty = true;
+    rc = rebuild(b);
+    if (rc) {
+        const std::string why(g_err);
+        b->form = old;
+        b->dirty = true;
+        (void)rebuild(b);
+        return fail(rc, why);
+    }
+    return REWL_OK;
+}
+
 int rewl_batch_set_graph(rewl_batch *b, int rounds_per_graph)
 {
     if (!b || rounds_per_graph < 0) return fail(REWL_EINVAL, "bad arguments");
@@ -1405,6 +1495,7 @@ int rewl_batch_get_timing(rewl_batch *b, double *sweep_ms, int64_t *sweep_launch
 }
 
 void rewl_batch_destroy(rewl_batch *b) { free_batch(b); }
+
 // ------------------------------------------------------------------- server
 }  // extern "C"
 

@@ -71,10 +71,36 @@ struct BatchDev {
     const WinItem *win;
     const WinItem *pair;
     int n_runs, n_sweep, n_win, n_pair;
-    int P;          // walkers per wave in the sweep (1, 2, 4, 8, 16, 32, 64)
+    int P;          // walkers per wave in the sweep (1, 2, 4, 8)
     int max_N, max_W;
     int j_words;    // coupling words per site of the batch's runs (0, 1 EA, 2 EA3)
     int region;     // LDS stride of the walkers' regions: sweep_region(max_W, max_N, 64/P)
+    int pwaves;     // persistent form: waves per work-group (one run each)
+};
+
+// Persistent form: one work-group holds one run for several rounds.  At most
+// kPersistMaxWaves waves of P walkers and kPersistMaxWalkers walkers per run;
+// the run's small state lives in PersistShared (static LDS) next to the
+// walkers' regions.
+constexpr int kPersistMaxWalkers = 64;
+constexpr int kPersistMaxWaves = 8;
+
+struct PersistShared {
+    int E[kPersistMaxWalkers];
+    int flat[kPersistMaxWalkers];
+    unsigned long long t[kPersistMaxWalkers];
+    double lnf[kPersistMaxWalkers];
+    int done[kPersistMaxWalkers];
+    int phase[kPersistMaxWalkers];
+    int merge[kPersistMaxWalkers];
+    long long first[kPersistMaxWalkers];   // per window: round of the first merge
+    long long finish[kPersistMaxWalkers];  // per window: round it finished in
+    unsigned long long ex_prop[kPersistMaxWalkers], ex_acc[kPersistMaxWalkers];
+    // exchange: partner permutations (pairs x m <= walkers / 2) and the
+    // accepted swaps of one step
+    int perm[kPersistMaxWalkers / 2];
+    int sw_i[kPersistMaxWalkers / 2], sw_j[kPersistMaxWalkers / 2];
+    int n_swap, all_done;
 };
 
 // Proposals staged per block of the sweep (one per lane), decoded so that
@@ -129,11 +155,27 @@ inline int model_j_words(int model) { return model == 2 ? 1 : (model == 3 ? 2 : 
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// launchers (rewl_kernels.hip)
+// most dynamic LDS a persistent work-group may take: the CU's LDS less 8 KiB,
+// which holds PersistShared (4.7 KB) with room for the allocation granule
+constexpr size_t kPersistMaxDynLds = kMaxLds - 8 * 1024;
+
+// dynamic LDS bytes of a persistent work-group: `waves` waves of P walkers'
+// regions, then the run's couplings (the static PersistShared comes on top)
+inline size_t persist_lds_bytes(int P, int waves, int W, int N, int j_words)
+{
+    return (size_t)waves * P * sweep_region(W, N, kWave / P) + (size_t)j_words * 4 * (size_t)N;
+}
+
+// launchers (rewl_kernels.hip); a launcher that returns -3 leaves the failed
+// HIP call and its error in rewl_launch_error() (per thread)
+const char *rewl_launch_error(void);
 int rewl_launch_init(const RunDesc &a, void *stream);
 // One round of every run in the batch: sweep, flatness/merge, exchange,
 // round counters.  ev0/ev1 (hipEvent_t or NULL) bracket the sweep launch.
 int rewl_launch_round(const BatchDev &b, void *stream, void *ev0, void *ev1);
+// `rounds` rounds of every run of the batch in one launch of the persistent
+// kernel (one work-group per run, b.pwaves waves each); ev0/ev1 bracket it
+int rewl_launch_persist(const BatchDev &b, long long rounds, void *stream, void *ev0, void *ev1);
 // per run of the batch: out_d[i] = 1 when every window of run i is done
 int rewl_launch_status(const BatchDev &b, int *out_d, void *stream);
 int rewl_launch_selftest_philox(const uint32_t *ctr_d, uint32_t k0, uint32_t k1, uint32_t *out_d,

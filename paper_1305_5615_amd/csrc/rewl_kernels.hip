@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstdio>
 
 #include "rewl_device.h"
 #include "rewl_internal.h"
@@ -29,6 +30,21 @@
 using namespace rewl;
 
 namespace {
+
+// the last failed HIP call of a launcher on this thread, for error messages
+thread_local char g_launch_err[256];
+
+int launch_fail(hipError_t e, const char *what)
+{
+    std::snprintf(g_launch_err, sizeof g_launch_err, "%s: %s", what, hipGetErrorString(e));
+    return -3;
+}
+
+int launch_status(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : launch_fail(e, what);
+}
 
 constexpr int kIsing = 0, kPotts = 1, kEA = 2, kEA3 = 3;
 
@@ -280,79 +296,142 @@ __device__ __forceinline__ unsigned int group_sum(unsigned int v)
 // energy change is 8 (Ising, +-J: 2 bins of 4) or 4 (Potts: 4 bins of 1)
 constexpr int kGuard = 4;
 
+// LDS region of one walker in a sweep work-group (the sizes of
+// sweep_walker_lds): ln g with kGuard guard bins on either side, H, the staged
+// proposals (G + 2), the per-step bin records, the per-site G-bit proposal
+// masks, the spins.
+template <int G>
+struct WalkerLds {
+    double *lng;                  // lng[0] is the window's first bin
+    uint32_t *H;
+    Prop *stage;
+    uint32_t *post;
+    typename TagOf<G>::T *tag;
+    int8_t *sp;
+};
+
+template <int G>
+__device__ __forceinline__ WalkerLds<G> walker_lds(unsigned char *mine, int max_W, int max_N)
+{
+    using TagT = typename TagOf<G>::T;
+    WalkerLds<G> r;
+    r.lng = reinterpret_cast<double *>(mine) + kGuard;
+    r.H = reinterpret_cast<uint32_t *>(mine + up16((size_t)(max_W + 2 * kGuard) * 8));
+    r.stage = reinterpret_cast<Prop *>(reinterpret_cast<unsigned char *>(r.H) +
+                                       up16((size_t)max_W * 4));
+    r.post = reinterpret_cast<uint32_t *>(r.stage + G + 2);
+    r.tag = reinterpret_cast<TagT *>(reinterpret_cast<unsigned char *>(r.post) +
+                                     up16((size_t)G * 4));
+    r.sp = reinterpret_cast<int8_t *>(reinterpret_cast<unsigned char *>(r.tag) +
+                                      up16((size_t)max_N * sizeof(TagT)));
+    return r;
+}
+
+// Orders the LDS writes of a wave's lanes before the reads of other lanes of
+// the same wave.  A wave's LDS instructions execute in order, so this only has
+// to keep the compiler from moving accesses across it; other waves of the
+// work-group are not waited for.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// HBM -> LDS: a walker's ln g (guard bins of +inf on either side: a move that
+// leaves the window meets +inf and is rejected by the ordinary test), H and
+// spins, and its proposal masks cleared.  The G lanes of its group share the
+// copy.
+template <int G>
+__device__ __forceinline__ void walker_load(const RunDesc &a, const WalkerLds<G> &L, int w,
+                                            int W, int gl)
+{
+    using TagT = typename TagOf<G>::T;
+    const double *lng_g = a.lng + (size_t)w * a.Wmax;
+    const uint32_t *H_g = a.H + (size_t)w * a.Wmax;
+    for (int i = gl; i < W; i += G) {
+        L.lng[i] = lng_g[i];
+        L.H[i] = H_g[i];
+    }
+    if (gl < kGuard) {
+        L.lng[-1 - gl] = __builtin_inf();
+        L.lng[W + gl] = __builtin_inf();
+    }
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(a.spins + (size_t)w * a.Npad);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(L.sp);
+    for (int i = gl; i < (a.N + 3) / 4; i += G) dst[i] = src[i];
+    for (int i = gl; i < a.N; i += G) L.tag[i] = (TagT)0;
+}
+
+// LDS -> HBM: the walker's ln g, H and spins
+template <int G>
+__device__ __forceinline__ void walker_store(const RunDesc &a, const WalkerLds<G> &L, int w,
+                                             int W, int gl)
+{
+    double *lng_g = a.lng + (size_t)w * a.Wmax;
+    uint32_t *H_g = a.H + (size_t)w * a.Wmax;
+    for (int i = gl; i < W; i += G) {
+        lng_g[i] = L.lng[i];
+        H_g[i] = L.H[i];
+    }
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(L.sp);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(a.spins + (size_t)w * a.Npad);
+    for (int i = gl; i < (a.N + 3) / 4; i += G) dst[i] = src[i];
+}
+
+// the two proposals past the last of a block, read ahead by the in-order
+// pass: zero moves
+template <int G>
+__device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, const unsigned char *wbase,
+                                             int gl)
+{
+    const uint32_t sp_base = (uint32_t)(reinterpret_cast<const unsigned char *>(L.sp) - wbase);
+    for (int i = gl; i < 2; i += G) L.stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
+}
+
 // RP: the per-step bin records (bin | accepted, for the H update at the end
 // of a block) are kept in a register of the lane that drew the attempt rather
 // than stored to LDS.  That costs VALU work per step and saves an LDS store;
 // it measured faster when several waves share a CU's LDS and slower with one
 // wave per CU, so the launcher picks it by the number of waves.
+//
+// S attempts of the walker of this lane's group (standard-WL paragraph), its
+// state in LDS at L; wbase is the start of the wave's LDS regions, against
+// which the pass addresses ln g and the spins.  live: the walker exists and its
+// window is running (a group that is not live only keeps the wave's lanes in
+// step).  Returns the walker's bin after the attempts (window-local) and adds
+// its accepted moves to acc.
 template <int MODEL, int P, bool RP>
-__device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
-                                           const BatchDev &bd, unsigned char *smem)
+__device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *wbase,
+                                              const WalkerLds<kWave / P> &L, const uint32_t *J_s,
+                                              int w, bool live, int W, int b0, double lnf,
+                                              bool one_over_t, unsigned long long t0,
+                                              unsigned int &acc)
 {
     constexpr int G = kWave / P;
     using TagT = typename TagOf<G>::T;
     constexpr int STEP = Step<MODEL>::value;
     constexpr int ADDR_PER_E = 8 / STEP;   // bytes of ln g per energy unit
-    const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+    const int lane = threadIdx.x & (kWave - 1), gl = lane % G;
     const int N = a.N, q = a.q;
-    const int w = it.w0 + grp;
-    const int k = w / a.m;
-    // a walker group is live when it exists and its window is still running
-    const bool live = grp < it.count && !a.done[k];
-    const size_t region = (size_t)bd.region;
-    unsigned char *mine = smem + (size_t)grp * region;
-    // ln g of the window with kGuard bins of +inf on either side: a move that
-    // leaves the window meets +inf and is rejected by the ordinary test
-    double *lng_s = reinterpret_cast<double *>(mine) + kGuard;
-    uint32_t *H_s = reinterpret_cast<uint32_t *>(mine + up16((size_t)(bd.max_W + 2 * kGuard) * 8));
-    Prop *stage = reinterpret_cast<Prop *>(reinterpret_cast<unsigned char *>(H_s) +
-                                           up16((size_t)bd.max_W * 4));
-    uint32_t *post_s = reinterpret_cast<uint32_t *>(stage + G + 2);
-    TagT *tag = reinterpret_cast<TagT *>(reinterpret_cast<unsigned char *>(post_s) +
-                                         up16((size_t)G * 4));
-    int8_t *sp = reinterpret_cast<int8_t *>(reinterpret_cast<unsigned char *>(tag) +
-                                            up16((size_t)bd.max_N * sizeof(TagT)));
-    uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)P * region);
-    const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - smem);
-    const uint32_t lng_base = (uint32_t)(reinterpret_cast<unsigned char *>(lng_s) - smem);
+    // a wave none of whose walkers is live has nothing to do
+    if (__builtin_amdgcn_ballot_w64(live) == 0) return b0;
+    double *lng_s = L.lng;
+    uint32_t *H_s = L.H;
+    Prop *stage = L.stage;
+    uint32_t *post_s = L.post;
+    TagT *tag = L.tag;
+    int8_t *sp = L.sp;
+    const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - wbase);
+    const uint32_t lng_base = (uint32_t)(reinterpret_cast<unsigned char *>(lng_s) - wbase);
 
-    const int lo = live ? a.lo[k] : 0;
-    const int W = live ? a.hi[k] - lo + 1 : 1;
-    double *lng_g = a.lng + (size_t)w * a.Wmax;
-    uint32_t *H_g = a.H + (size_t)w * a.Wmax;
-    int8_t *sp_g = a.spins + (size_t)w * a.Npad;
-    if (live) {
-        for (int i = gl; i < W; i += G) {
-            lng_s[i] = lng_g[i];
-            H_s[i] = H_g[i];
-        }
-        if (gl < kGuard) {
-            lng_s[-1 - gl] = __builtin_inf();
-            lng_s[W + gl] = __builtin_inf();
-        }
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(sp_g);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(sp);
-        for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
-        for (int i = gl; i < N; i += G) tag[i] = (TagT)0;
-    }
-    for (int i = gl; i < 2; i += G) stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
-    constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);  // coupling words per site
-    for (int i = lane; i < JW * N; i += kWave) J_s[i] = a.J4[i];
-    __syncthreads();
-
-    const int elo = a.e_min + lo * STEP;
-    const double lnf = live ? a.lnf[k] : 0.0;
     // the 1/t rule: ln f = W / t after each attempt, t = attempts made so far
-    const bool one_over_t = live && a.phase[k] != 0;
     const double Wd = (double)W;
-    const unsigned long long t0 = live ? a.t[w] : 0ull;
     const long long S = a.S;
     // chain state, identical in every lane of the group: LDS byte offset of
     // the current bin's ln g, and its value
-    const int b0 = live ? (a.E[w] - elo) / STEP : 0;
     uint32_t baddr = lng_base + (uint32_t)b0 * 8u;
     double gcur = live ? lng_s[b0] : 0.0;
-    unsigned int acc = 0;
     const uint64_t bit = 1ull << gl;
 
     // state-independent part of an attempt: Philox draw, site, neighbours,
@@ -430,7 +509,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
             // records past the last attempt: a zero move, read ahead only
             stage[gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
         }
-        __syncthreads();
+        wave_sync();
         if (active) tag[cur.site] = (TagT)0;
         // draws of the next block: with several walkers per wave, in pieces
         // between the steps of the in-order pass below; with one, whole here.
@@ -471,7 +550,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 return f;
             };
             auto ld = [&](uint32_t addr) {
-                return *reinterpret_cast<const double *>(smem + addr);
+                return *reinterpret_cast<const double *>(wbase + addr);
             };
             Rec r0 = fetch(0), r1 = fetch(1);
             // ln g at the next attempt's target, loaded before the current
@@ -533,8 +612,8 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
                 const double gsel = pick(accept, gn, gcur);
                 gnx = ld(baddr + (uint32_t)r1.d);
                 gcur = gsel + r0.lnf;
-                *reinterpret_cast<double *>(smem + baddr) = gcur;
-                smem[r0.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
+                *reinterpret_cast<double *>(wbase + baddr) = gcur;
+                wbase[r0.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
                 // bin after attempt j and its acceptance, for lane j's H update
                 if constexpr (RP)
                     post = (gl == j) ? (baddr | (accept ? 1u : 0u)) : post;
@@ -567,21 +646,49 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
         }
         // (a block shorter than G is the last one: its next draws are unused)
         cur = nxt.out;
-        __syncthreads();
+        wave_sync();
     }
+    return (int)((baddr - lng_base) >> 3);
+}
 
+// One round's sweep of one wave of a launch (a group of P walkers of one run):
+// load the walkers' state into LDS, S attempts each, store it back.
+template <int MODEL, int P, bool RP>
+__device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it,
+                                           const BatchDev &bd, unsigned char *smem)
+{
+    constexpr int G = kWave / P;
+    constexpr int STEP = Step<MODEL>::value;
+    const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+    const int N = a.N;
+    const int w = it.w0 + grp;
+    const int k = w / a.m;
+    // a walker group is live when it exists and its window is still running
+    const bool live = grp < it.count && !a.done[k];
+    const WalkerLds<G> L = walker_lds<G>(smem + (size_t)grp * bd.region, bd.max_W, bd.max_N);
+    uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)P * bd.region);
+    const int lo = live ? a.lo[k] : 0;
+    const int W = live ? a.hi[k] - lo + 1 : 1;
+    if (live) walker_load<G>(a, L, w, W, gl);
+    stage_guards<G>(L, smem, gl);
+    constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);  // coupling words per site
+    for (int i = lane; i < JW * N; i += kWave) J_s[i] = a.J4[i];
+    __syncthreads();
+
+    const int elo = a.e_min + lo * STEP;
+    const double lnf = live ? a.lnf[k] : 0.0;
+    const bool one_over_t = live && a.phase[k] != 0;
+    const unsigned long long t0 = live ? a.t[w] : 0ull;
+    const int b0 = live ? (a.E[w] - elo) / STEP : 0;
+    unsigned int acc = 0;
+    const int b = sweep_attempts<MODEL, P, RP>(a, smem, L, J_s, w, live, W, b0, lnf, one_over_t,
+                                               t0, acc);
     if (live) {
-        for (int i = gl; i < W; i += G) {
-            lng_g[i] = lng_s[i];
-            H_g[i] = H_s[i];
-        }
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(sp);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(sp_g);
-        for (int i = gl; i < (N + 3) / 4; i += G) dst[i] = src[i];
+        walker_store<G>(a, L, w, W, gl);
         const unsigned int acc_w = group_sum<G>(acc);
         if (gl == 0) {
-            a.E[w] = elo + (int)((baddr - lng_base) >> 3) * STEP;
-            a.t[w] = t0 + (unsigned long long)S;
+            a.E[w] = elo + b * STEP;
+            a.t[w] = t0 + (unsigned long long)a.S;
             a.n_acc[w] += acc_w;
         }
     }
@@ -704,6 +811,60 @@ __global__ __launch_bounds__(256) void flat_merge_kernel(BatchDev bd)
 // and walker pi[a] of window k+1 (configuration Y) swap configurations iff
 // both energies lie in both windows and
 // ln u < [ln g_i(E_X) - ln g_i(E_Y)] + [ln g_j(E_Y) - ln g_j(E_X)]   (Eq. (1)).
+// One thread decides the pair.  get_E(w) / set_E(w, E): walker w's energy;
+// lng_at(w, b): walker w's ln g at window-local bin b; swapped(wi, wj): the
+// configurations of the two walkers are to be exchanged.  perm: m ints.
+// Returns the accepted swaps (the pair made m proposals).
+template <class GetE, class SetE, class LngAt, class Swapped>
+__device__ unsigned long long exchange_pair(const RunDesc &a, int k, long long round, int *perm,
+                                            GetE get_E, SetE set_E, LngAt lng_at,
+                                            Swapped swapped)
+{
+    const int m = a.m;
+    uint32_t buf[4] = {0, 0, 0, 0};
+    uint32_t call = 0;
+    int idx = 4;
+    auto next = [&]() -> uint32_t {
+        if (idx == 4) {
+            const U4 r = philox((uint32_t)round, (uint32_t)((unsigned long long)round >> 32),
+                                (uint32_t)k, 3u | (call << 8), a.key0, a.key1);
+            buf[0] = r.x; buf[1] = r.y; buf[2] = r.z; buf[3] = r.w;
+            call += 1;
+            idx = 0;
+        }
+        return buf[idx++];
+    };
+    for (int s = 0; s < m; ++s) perm[s] = s;
+    for (int s = m - 1; s >= 1; --s) {
+        const int j = (int)mulhi32(next(), (uint32_t)(s + 1));
+        const int x = perm[s];
+        perm[s] = perm[j];
+        perm[j] = x;
+    }
+    const int lo_i = a.lo[k], hi_i = a.hi[k], lo_j = a.lo[k + 1], hi_j = a.hi[k + 1];
+    unsigned long long acc = 0;
+    for (int s = 0; s < m; ++s) {
+        const uint32_t hi = next();
+        const uint32_t lo = next();
+        const double thr = ln_u(hi, lo);
+        const int wi = k * m + s, wj = (k + 1) * m + perm[s];
+        const int EX = get_E(wi), EY = get_E(wj);
+        const int bX = (EX - a.e_min) / a.step, bY = (EY - a.e_min) / a.step;
+        if (bX < lo_j || bX > hi_j || bY < lo_i || bY > hi_i) continue;
+        const double lnP = (lng_at(wi, bX - lo_i) - lng_at(wi, bY - lo_i)) +
+                           (lng_at(wj, bY - lo_j) - lng_at(wj, bX - lo_j));
+        if (thr < lnP) {
+            set_E(wi, EY);
+            set_E(wj, EX);
+            swapped(wi, wj);
+            ++acc;
+        }
+    }
+    return acc;
+}
+
+// One work-group per window-pair slot: thread 0 decides, all threads swap
+// the accepted configurations in HBM.
 __global__ __launch_bounds__(256) void exchange_kernel(BatchDev bd)
 {
     const WinItem it = bd.pair[blockIdx.x];
@@ -712,53 +873,19 @@ __global__ __launch_bounds__(256) void exchange_kernel(BatchDev bd)
     const int k = 2 * it.k + (int)(round & 1);
     if (k + 1 >= a.h) return;
     if (a.done[k] || a.done[k + 1]) return;
-    const int m = a.m;
     __shared__ int sh_n, sh_wi[64], sh_wj[64], perm[64];
     if (threadIdx.x == 0) {
-        uint32_t buf[4] = {0, 0, 0, 0};
-        uint32_t call = 0;
-        int idx = 4;
-        auto next = [&]() -> uint32_t {
-            if (idx == 4) {
-                const U4 r = philox((uint32_t)round, (uint32_t)((unsigned long long)round >> 32),
-                                    (uint32_t)k, 3u | (call << 8), a.key0, a.key1);
-                buf[0] = r.x; buf[1] = r.y; buf[2] = r.z; buf[3] = r.w;
-                call += 1;
-                idx = 0;
-            }
-            return buf[idx++];
-        };
-        for (int s = 0; s < m; ++s) perm[s] = s;
-        for (int s = m - 1; s >= 1; --s) {
-            const int j = (int)mulhi32(next(), (uint32_t)(s + 1));
-            const int x = perm[s];
-            perm[s] = perm[j];
-            perm[j] = x;
-        }
-        const int lo_i = a.lo[k], hi_i = a.hi[k], lo_j = a.lo[k + 1], hi_j = a.hi[k + 1];
         int n = 0;
-        unsigned long long acc = 0;
-        for (int s = 0; s < m; ++s) {
-            const uint32_t hi = next();
-            const uint32_t lo = next();
-            const double thr = ln_u(hi, lo);
-            const int wi = k * m + s, wj = (k + 1) * m + perm[s];
-            const int EX = a.E[wi], EY = a.E[wj];
-            const int bX = (EX - a.e_min) / a.step, bY = (EY - a.e_min) / a.step;
-            if (bX < lo_j || bX > hi_j || bY < lo_i || bY > hi_i) continue;
-            const double *gi = a.lng + (size_t)wi * a.Wmax;
-            const double *gj = a.lng + (size_t)wj * a.Wmax;
-            const double lnP = (gi[bX - lo_i] - gi[bY - lo_i]) + (gj[bY - lo_j] - gj[bX - lo_j]);
-            if (thr < lnP) {
-                a.E[wi] = EY;
-                a.E[wj] = EX;
+        const unsigned long long acc = exchange_pair(
+            a, k, round, perm, [&](int w) { return a.E[w]; },
+            [&](int w, int E) { a.E[w] = E; },
+            [&](int w, int b) { return a.lng[(size_t)w * a.Wmax + b]; },
+            [&](int wi, int wj) {
                 sh_wi[n] = wi;
                 sh_wj[n] = wj;
                 ++n;
-                ++acc;
-            }
-        }
-        a.ex_prop[k] += (unsigned long long)m;
+            });
+        a.ex_prop[k] += (unsigned long long)a.m;
         a.ex_acc[k] += acc;
         sh_n = n;
     }
@@ -772,6 +899,242 @@ __global__ __launch_bounds__(256) void exchange_kernel(BatchDev bd)
             x[i] = y[i];
             y[i] = v;
         }
+    }
+}
+
+// --------------------------------------------------------- persistent form
+// One work-group per run, for runs whose walkers all fit one work-group: the
+// whole run stays in LDS for `rounds` rounds (sweep, flatness, merges,
+// exchange, each a work-group step between barriers), the hierarchy of the
+// parallel-scheme paragraph (h windows x m walkers) held by one CU.  Wave v
+// sweeps walkers vP .. vP+P-1 exactly as sweep_kernel does; walker w's LDS
+// region is the w-th of the work-group.  The results are those of the same
+// rounds launched kernel by kernel.
+template <int MODEL, int P, bool RP>
+__device__ __forceinline__ void persist_body(const RunDesc &a, const BatchDev &bd,
+                                             unsigned char *smem, long long rounds,
+                                             PersistShared &ps)
+{
+    constexpr int G = kWave / P;
+    constexpr int STEP = Step<MODEL>::value;
+    const int tid = threadIdx.x, nthr = blockDim.x, wave = tid / kWave, lane = tid % kWave;
+    const int grp = lane / G, gl = lane % G;
+    const int N = a.N, m = a.m, h = a.h, nw = a.nw;
+    const size_t region = (size_t)bd.region;
+    const int w = wave * P + grp;
+    const bool exists = w < nw;
+    const int k = exists ? w / m : 0;
+    unsigned char *wbase = smem + (size_t)wave * P * region;
+    const WalkerLds<G> L = walker_lds<G>(wbase + (size_t)grp * region, bd.max_W, bd.max_N);
+    uint32_t *J_s = reinterpret_cast<uint32_t *>(smem + (size_t)(nthr / kWave) * P * region);
+    auto lng_of = [&](int v) { return walker_lds<G>(smem + (size_t)v * region, bd.max_W, bd.max_N); };
+    const int lo = exists ? a.lo[k] : 0;
+    const int W = exists ? a.hi[k] - lo + 1 : 1;
+    const int elo = a.e_min + lo * STEP;
+
+    if (exists) walker_load<G>(a, L, w, W, gl);
+    stage_guards<G>(L, wbase, gl);
+    constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);
+    for (int i = tid; i < JW * N; i += nthr) J_s[i] = a.J4[i];
+    for (int i = tid; i < nw; i += nthr) {
+        ps.E[i] = a.E[i];
+        ps.flat[i] = a.flat[i];
+        ps.t[i] = a.t[i];
+    }
+    for (int i = tid; i < h; i += nthr) {
+        ps.lnf[i] = a.lnf[i];
+        ps.done[i] = a.done[i];
+        ps.phase[i] = a.phase[i];
+        ps.first[i] = a.first[i];
+        ps.finish[i] = a.finish[i];
+        ps.ex_prop[i] = a.ex_prop[i];
+        ps.ex_acc[i] = a.ex_acc[i];
+    }
+    if (tid == 0) ps.n_swap = 0;
+    // from here to the write-back every access is to LDS: no device-memory
+    // operation stays in flight across the rounds' waits on LDS loads
+    __syncthreads();
+
+    const long long round0 = *a.round;
+    const bool pow2 = (m & (m - 1)) == 0;
+    const double inv = 1.0 / (double)m;
+    unsigned int acc_all = 0;
+    for (long long r = 0; r < rounds; ++r) {
+        // a finished run changes no more (its round counter still advances)
+        if (tid == 0) {
+            int all = 1;
+            for (int kk = 0; kk < h; ++kk) all &= (ps.done[kk] != 0);
+            ps.all_done = all;
+        }
+        __syncthreads();
+        if (ps.all_done) break;
+        const long long round = round0 + r;
+
+        // (1) sweep: S attempts by every walker of an unfinished window
+        {
+            const bool live = exists && !ps.done[k];
+            const unsigned long long t0 = exists ? ps.t[w] : 0ull;
+            const int b0 = exists ? (ps.E[w] - elo) / STEP : 0;
+            unsigned int acc = 0;
+            const int b = sweep_attempts<MODEL, P, RP>(a, wbase, L, J_s, w, live, W, b0,
+                                                       live ? ps.lnf[k] : 0.0,
+                                                       live && ps.phase[k] != 0, t0, acc);
+            acc_all += acc;
+            if (live && gl == 0) {
+                ps.E[w] = elo + b * STEP;
+                ps.t[w] = t0 + (unsigned long long)a.S;
+            }
+        }
+        __syncthreads();
+
+        // (2) flatness of each walker of a running window on the halving rule
+        // that is not flat yet: min H * n >= p * sum H over its visited bins
+        if (exists && !ps.done[k] && !ps.phase[k] && !ps.flat[w]) {
+            unsigned long long sum = 0;
+            unsigned int hmin = 0xFFFFFFFFu, n = 0;
+            for (int i = gl; i < W; i += G) {
+                if (L.lng[i] > 0.0) {
+                    const uint32_t hv = L.H[i];
+                    sum += hv;
+                    n += 1;
+                    hmin = hv < hmin ? hv : hmin;
+                }
+            }
+            for (int off = G / 2; off > 0; off >>= 1) {
+                sum += __shfl_xor(sum, off);
+                n += __shfl_xor(n, off);
+                const unsigned int o = __shfl_xor(hmin, off);
+                hmin = o < hmin ? o : hmin;
+            }
+            if (gl == 0)
+                ps.flat[w] = (n > 0) && ((double)hmin * (double)n >= a.flat_p * (double)sum);
+        }
+        __syncthreads();
+
+        // (3) schedule of each window whose m walkers are all flat (or that
+        // follows the 1/t rule): flags cleared, ln f halved (or W/t), done
+        // below ln f_final
+        if (tid < h) {
+            const int kk = tid;
+            int mg = 0;
+            if (!ps.done[kk]) {
+                int all = 1;
+                for (int s = 0; s < m; ++s) all &= (ps.flat[kk * m + s] != 0);
+                if (all || ps.phase[kk]) {
+                    mg = 1;
+                    for (int s = 0; s < m; ++s) ps.flat[kk * m + s] = 0;
+                    if (ps.first[kk] < 0) ps.first[kk] = round;
+                    const int Wk = a.hi[kk] - a.lo[kk] + 1;
+                    const double Wt = (double)Wk / (double)ps.t[kk * m];
+                    double nl;
+                    if (ps.phase[kk]) {
+                        nl = Wt;
+                    } else {
+                        nl = ps.lnf[kk] * 0.5;
+                        if (a.schedule == 1 && nl < Wt) {
+                            ps.phase[kk] = 1;
+                            nl = Wt;
+                        }
+                    }
+                    ps.lnf[kk] = nl;
+                    if (nl < a.lnf_final) {
+                        ps.done[kk] = 1;
+                        ps.finish[kk] = round;
+                    }
+                }
+            }
+            ps.merge[kk] = mg;
+        }
+        __syncthreads();
+
+        // (4) merge: every walker of the window gets the mean of their ln g
+        // (summed in slot order), H <- 0
+        for (int kk = 0; kk < h; ++kk) {
+            if (!ps.merge[kk]) continue;
+            const int Wk = a.hi[kk] - a.lo[kk] + 1;
+            for (int i = tid; i < Wk; i += nthr) {
+                double sum = 0.0;
+                for (int s = 0; s < m; ++s) sum = sum + lng_of(kk * m + s).lng[i];
+                const double mean = pow2 ? sum * inv : sum / (double)m;
+                for (int s = 0; s < m; ++s) {
+                    const WalkerLds<G> v = lng_of(kk * m + s);
+                    v.lng[i] = mean;
+                    v.H[i] = 0u;
+                }
+            }
+        }
+        __syncthreads();
+
+        // (5) exchange between windows (kk, kk+1), kk = round mod 2 + 2 slot
+        if (tid < h / 2) {
+            const int kk = 2 * tid + (int)(round & 1);
+            if (kk + 1 < h && !ps.done[kk] && !ps.done[kk + 1]) {
+                const unsigned long long acc = exchange_pair(
+                    a, kk, round, ps.perm + tid * m, [&](int v) { return ps.E[v]; },
+                    [&](int v, int E) { ps.E[v] = E; },
+                    [&](int v, int b) { return lng_of(v).lng[b]; },
+                    [&](int wi, int wj) {
+                        const int at = atomicAdd(&ps.n_swap, 1);
+                        ps.sw_i[at] = wi;
+                        ps.sw_j[at] = wj;
+                    });
+                ps.ex_prop[kk] += (unsigned long long)m;
+                ps.ex_acc[kk] += acc;
+            }
+        }
+        __syncthreads();
+        // (6) the accepted configuration swaps (disjoint pairs of walkers)
+        const int nsw = ps.n_swap;
+        const int words = (N + 3) / 4;
+        for (int p = 0; p < nsw; ++p) {
+            uint32_t *x = reinterpret_cast<uint32_t *>(lng_of(ps.sw_i[p]).sp);
+            uint32_t *y = reinterpret_cast<uint32_t *>(lng_of(ps.sw_j[p]).sp);
+            for (int i = tid; i < words; i += nthr) {
+                const uint32_t v = x[i];
+                x[i] = y[i];
+                y[i] = v;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) ps.n_swap = 0;
+    }
+    __syncthreads();
+
+    // LDS -> HBM
+    if (exists) {
+        walker_store<G>(a, L, w, W, gl);
+        const unsigned int acc_w = group_sum<G>(acc_all);
+        if (gl == 0) a.n_acc[w] += acc_w;
+    }
+    for (int i = tid; i < nw; i += nthr) {
+        a.E[i] = ps.E[i];
+        a.flat[i] = ps.flat[i];
+        a.t[i] = ps.t[i];
+    }
+    for (int i = tid; i < h; i += nthr) {
+        a.lnf[i] = ps.lnf[i];
+        a.done[i] = ps.done[i];
+        a.phase[i] = ps.phase[i];
+        a.first[i] = ps.first[i];
+        a.finish[i] = ps.finish[i];
+        a.ex_prop[i] = ps.ex_prop[i];
+        a.ex_acc[i] = ps.ex_acc[i];
+    }
+    if (tid == 0) *a.round = round0 + rounds;
+}
+
+template <int P, bool RP>
+__global__ __launch_bounds__(kWave * kPersistMaxWaves) void persist_kernel(BatchDev bd,
+                                                                           long long rounds)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ PersistShared ps;
+    const RunDesc a = bd.runs[blockIdx.x];
+    switch (a.model) {
+    case kIsing: persist_body<kIsing, P, RP>(a, bd, smem, rounds, ps); break;
+    case kPotts: persist_body<kPotts, P, RP>(a, bd, smem, rounds, ps); break;
+    case kEA: persist_body<kEA, P, RP>(a, bd, smem, rounds, ps); break;
+    default: persist_body<kEA3, P, RP>(a, bd, smem, rounds, ps); break;
     }
 }
 
@@ -817,12 +1180,13 @@ int launch_init_t(const RunDesc &a, hipStream_t s)
 {
     const size_t lds = kWave * sizeof(Move) + 8 * sizeof(int) +
                        (size_t)model_j_words(MODEL) * 4 * (size_t)a.N + (size_t)a.N + 16;
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -3;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&init_kernel<MODEL>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return launch_fail(e, "hipFuncSetAttribute(init_kernel)");
+    }
     hipLaunchKernelGGL(init_kernel<MODEL>, dim3(a.nw), dim3(256), lds, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status("init_kernel launch");
 }
 
 template <int P, bool RP>
@@ -833,10 +1197,10 @@ int launch_sweep_rp(const BatchDev &b, hipStream_t s, size_t lds)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -3;
     if (!attr_set[dev].load()) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P, RP>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kMaxLds) != hipSuccess)
-            return -3;
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<P, RP>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)kMaxLds);
+        if (e != hipSuccess) return launch_fail(e, "hipFuncSetAttribute(sweep_kernel)");
         attr_set[dev].store(true);
     }
     hipLaunchKernelGGL((sweep_kernel<P, RP>), dim3(b.n_sweep), dim3(kWave), lds, s, b);
@@ -866,7 +1230,58 @@ int launch_sweep_t(const BatchDev &b, hipStream_t s, size_t lds)
     return launch_sweep_rp<P, false>(b, s, lds);
 }
 
+template <int P, bool RP>
+int launch_persist_rp(const BatchDev &b, hipStream_t s, size_t lds, long long rounds)
+{
+    static std::atomic<bool> attr_set[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -3;
+    if (!attr_set[dev].load()) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&persist_kernel<P, RP>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)kPersistMaxDynLds);
+        if (e != hipSuccess) return launch_fail(e, "hipFuncSetAttribute(persist_kernel)");
+        attr_set[dev].store(true);
+    }
+    hipLaunchKernelGGL((persist_kernel<P, RP>), dim3(b.n_runs), dim3(kWave * b.pwaves), lds, s, b,
+                       rounds);
+    return 0;
+}
+
+template <int P>
+int launch_persist_t(const BatchDev &b, hipStream_t s, size_t lds, long long rounds)
+{
+    // as for the sweep: several waves per CU keep the bin records in registers
+    if ((long long)b.n_runs * b.pwaves > device_cus())
+        return launch_persist_rp<P, true>(b, s, lds, rounds);
+    return launch_persist_rp<P, false>(b, s, lds, rounds);
+}
+
 }  // namespace
+
+int rewl_launch_persist(const BatchDev &b, long long rounds, void *stream, void *ev0, void *ev1)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0 = reinterpret_cast<hipEvent_t>(ev0), e1 = reinterpret_cast<hipEvent_t>(ev1);
+    if (b.n_runs <= 0 || rounds <= 0) return 0;
+    if (b.pwaves < 1 || b.pwaves > kPersistMaxWaves) return -1;
+    const size_t lds = persist_lds_bytes(b.P, b.pwaves, b.max_W, b.max_N, b.j_words);
+    if (lds > kPersistMaxDynLds) return -1;
+    if (e0 && hipEventRecord(e0, s) != hipSuccess) return -3;
+    int rc;
+    switch (b.P) {
+    case 1: rc = launch_persist_t<1>(b, s, lds, rounds); break;
+    case 2: rc = launch_persist_t<2>(b, s, lds, rounds); break;
+    case 4: rc = launch_persist_t<4>(b, s, lds, rounds); break;
+    case 8: rc = launch_persist_t<8>(b, s, lds, rounds); break;
+    default: return -1;
+    }
+    if (rc) return rc;
+    if (e1 && hipEventRecord(e1, s) != hipSuccess) return -3;
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+const char *rewl_launch_error(void) { return g_launch_err; }
 
 int rewl_launch_init(const RunDesc &a, void *stream)
 {
@@ -902,7 +1317,7 @@ int rewl_launch_round(const BatchDev &b, void *stream, void *ev0, void *ev1)
     if (b.n_pair > 0) hipLaunchKernelGGL(exchange_kernel, dim3(b.n_pair), dim3(256), 0, s, b);
     if (b.n_runs > 0)
         hipLaunchKernelGGL(advance_kernel, dim3((b.n_runs + 255) / 256), dim3(256), 0, s, b);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status("round launches");
 }
 
 int rewl_launch_status(const BatchDev &b, int *out_d, void *stream)
