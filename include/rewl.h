@@ -317,6 +317,37 @@ int rewl_server_result(rewl_server *s, int64_t id, double *out, int64_t cap, int
 int rewl_server_release(rewl_server *s, int64_t id);
 void rewl_server_destroy(rewl_server *s);
 
+/* ------------------------------------------------- allocation-free variant
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run that
+ * rewl_create_ex followed by rewl_step(rounds) would make, in one call that
+ * allocates nothing -- no hipMalloc, hipFree or other allocating routine, and
+ * no host heap either.  The caller passes the outputs, device arrays it owns:
+ *   E      walkers int32: energy of walker w = window * walkers_per_window + slot;
+ *   spins  walkers x spins_stride int8: walker w's configuration at
+ *          spins[w * spins_stride + site] (sites as in rewl_get_walker),
+ *          spins_stride >= n_sites and a multiple of 4;
+ *   lng, H walkers x bins_stride (double, uint32): walker w's window-local
+ *          ln g and histogram at [w * bins_stride + b], b = 0 .. window bins - 1,
+ *          bins_stride >= the widest window's bins (zeroed by the call
+ *          first, so unvisited bins hold 0).
+ * After the call's work on hip_stream has completed they hold exactly what
+ * rewl_get_walker reports for the same run made by rewl_create_ex and stepped
+ * `rounds` rounds.  Everything else the run needs (walker and window
+ * bookkeeping, couplings in kernel layout, launch tables) lives in one static
+ * device array of the library, 128 KiB on each device it runs on, held until
+ * the process ends (about 36 bytes per walker, 80 per window, 6 per site of a
+ * 2D glass and 11 of a 3D one); runs needing more (some 3000 walkers or more)
+ * and runs of more than 64 windows are REWL_EINVAL.
+ * The call waits for the start-up (REWL_EINIT as in rewl_create_ex), then
+ * queues the rounds and returns; the caller synchronises the stream before
+ * reading the outputs.  Every call on a device shares that device's array and
+ * overwrites it: calls that overlap on one device (other threads, or other
+ * streams not ordered after this one) race and give undefined results. */
+int rewl_run_noalloc(const rewl_params *p, int64_t rounds, int32_t *E, int8_t *spins,
+                     int64_t spins_stride, double *lng, uint32_t *H, int64_t bins_stride,
+                     void *hip_stream);
+
 const char *rewl_last_error(void);
 
 /* Diagnostics: evaluate the device's Philox4x32-10 block for n counters

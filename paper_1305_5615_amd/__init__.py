@@ -82,6 +82,7 @@ def lib():
         L.rewl_batch_set_walkers_per_wave.argtypes = [P, i32]
         L.rewl_batch_set_graph.argtypes = [P, i32]
         L.rewl_batch_set_form.argtypes = [P, i32]
+        L.rewl_run_noalloc.argtypes = [C.POINTER(Params), i64, P, P, i64, P, P, i64, P]
         L.rewl_batch_step.argtypes = [P, i64]
         L.rewl_batch_run.argtypes = [P, i64, C.POINTER(i64)]
         L.rewl_batch_done.argtypes = [P, P, i32]
@@ -533,6 +534,23 @@ class Server:
 
     def release(self, rid):
         _check(lib().rewl_server_release(self._h, int(rid)), "rewl_server_release")
+
+
+def run_noalloc(rounds, E, spins, lng, H, stream=None, **kw):
+    """rewl_run_noalloc: the run of kw stepped `rounds` rounds into the caller's
+    torch tensors E (int32, walkers), spins (int8, walkers x stride), lng
+    (float64, walkers x bins) and H (int32, walkers x bins), without any
+    allocation by the library (argument marshalling only)."""
+    import torch
+
+    p, keep = make_params(**kw)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().rewl_run_noalloc(C.byref(p), int(rounds), C.c_void_p(E.data_ptr()),
+                                  C.c_void_p(spins.data_ptr()), int(spins.shape[1]),
+                                  C.c_void_p(lng.data_ptr()), C.c_void_p(H.data_ptr()),
+                                  int(lng.shape[1]), C.c_void_p(s.cuda_stream)),
+           "rewl_run_noalloc")
+    del keep
 
 
 def selftest_philox(ctr, key):

@@ -1496,6 +1496,114 @@ int rewl_batch_get_timing(rewl_batch *b, double *sweep_ms, int64_t *sweep_launch
 
 void rewl_batch_destroy(rewl_batch *b) { free_batch(b); }
 
+// ------------------------------------------------- allocation-free entry point
+int rewl_run_noalloc(const rewl_params *p, int64_t rounds, int32_t *E, int8_t *spins,
+                     int64_t spins_stride, double *lng, uint32_t *H, int64_t bins_stride,
+                     void *hip_stream)
+{
+    if (!p || rounds < 0 || !E || !spins || !lng || !H)
+        return fail(REWL_EINVAL, "rewl_run_noalloc: NULL argument or negative rounds");
+    if (p->n_windows < 1 || p->n_windows > kNoAllocMaxWindows)
+        return fail(REWL_EINVAL, "rewl_run_noalloc: n_windows must be in [1, 64]");
+    Geometry g;  // its window vectors stay empty: the windows live in lo / hi
+    int64_t lo[kNoAllocMaxWindows], hi[kNoAllocMaxWindows];
+    int rc = validate_into(p, g, lo, hi);
+    if (rc) return rc;
+    if (spins_stride < g.N || spins_stride % 4 || bins_stride < g.Wmax)
+        return fail(REWL_EINVAL, "rewl_run_noalloc: spins_stride must be a multiple of 4 and "
+                                 ">= the sites, bins_stride >= the widest window's bins");
+    if ((uintptr_t)E % 4 || (uintptr_t)spins % 4 || (uintptr_t)lng % 8 || (uintptr_t)H % 4)
+        return fail(REWL_EINVAL, "rewl_run_noalloc: misaligned output array");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    // the scratch layout: launch tables, then the run's bookkeeping
+    const size_t nw = (size_t)g.nw, h = (size_t)p->n_windows, N = (size_t)g.N;
+    const bool glass = p->model == REWL_EA || p->model == REWL_EA3;
+    const size_t j_raw = glass ? (size_t)bonds_per_site(p->model) * N : 0;
+    const size_t j_words = (size_t)model_j_words(p->model);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 4), 256);
+        return at;
+    };
+    const size_t o_desc = take(sizeof(RunDesc)), o_sweep = take(nw * sizeof(SweepItem));
+    const size_t o_win = take(h * sizeof(WinItem)), o_pair = take(h / 2 * sizeof(WinItem));
+    const size_t o_t = take(nw * 8), o_flat = take(nw * 4), o_acc = take(nw * 8);
+    const size_t o_lnf = take(h * 8), o_done = take(h * 4), o_phase = take(h * 4);
+    const size_t o_fin = take(h * 8), o_first = take(h * 8), o_lo = take(h * 4), o_hi = take(h * 4);
+    const size_t o_exp = take(h * 8), o_exa = take(h * 8);
+    const size_t o_jraw = take(j_raw), o_j4 = take(j_words * 4 * N);
+    const size_t o_round = take(8), o_status = take(4);
+    if (off > kNoAllocScratch)
+        return fail(REWL_EINVAL, "rewl_run_noalloc: the run needs more than the 128 KiB of "
+                                 "device scratch (about 36 bytes per walker, 80 per window, "
+                                 "6 per site of a 2D glass, 11 of a 3D one)");
+    void *base = nullptr;
+    if (rewl_noalloc_scratch(&base)) return fail(REWL_EDEVICE, "rewl_run_noalloc: scratch lookup");
+    char *sc = (char *)base;
+    NoAllocSetup s{};
+    RunDesc &d = s.d;
+    fill_desc(d, p, g);
+    d.Npad = (int)spins_stride;
+    d.Wmax = (int)bins_stride;
+    d.spins = spins;
+    d.E = E;
+    d.lng = lng;
+    d.H = H;
+    d.t = (unsigned long long *)(sc + o_t);
+    d.flat = (int *)(sc + o_flat);
+    d.n_acc = (unsigned long long *)(sc + o_acc);
+    d.lnf = (double *)(sc + o_lnf);
+    d.done = (int *)(sc + o_done);
+    d.phase = (int *)(sc + o_phase);
+    d.finish = (long long *)(sc + o_fin);
+    d.first = (long long *)(sc + o_first);
+    d.lo = (int *)(sc + o_lo);
+    d.hi = (int *)(sc + o_hi);
+    d.ex_prop = (unsigned long long *)(sc + o_exp);
+    d.ex_acc = (unsigned long long *)(sc + o_exa);
+    d.J4 = (uint32_t *)(sc + o_j4);
+    d.round = (long long *)(sc + o_round);
+    d.status = (int *)(sc + o_status);
+    s.desc = (RunDesc *)(sc + o_desc);
+    s.sweep = (SweepItem *)(sc + o_sweep);
+    s.win = (WinItem *)(sc + o_win);
+    s.pair = (WinItem *)(sc + o_pair);
+    s.J_raw = (const int8_t *)(sc + o_jraw);
+    s.lnf_init = p->lnf_init;
+    for (int k = 0; k < p->n_windows; ++k) {
+        s.lo[k] = (int)lo[k];
+        s.hi[k] = (int)hi[k];
+    }
+    // the couplings as given (the caller's host array stays valid: this call
+    // waits for the stream before it returns from the start-up)
+    if (glass) HIP_TRY(hipMemcpyAsync(sc + o_jraw, p->couplings, j_raw, hipMemcpyHostToDevice, stream));
+    if (rewl_launch_noalloc_setup(s, stream)) return fail(REWL_EDEVICE, "rewl_run_noalloc: set-up launch");
+    if (rewl_launch_init(d, stream)) return fail(REWL_EDEVICE, "rewl_run_noalloc: start-up launch");
+    int status = 0;
+    HIP_TRY(hipMemcpyAsync(&status, d.status, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (status) return fail(REWL_EINIT, "rewl_run_noalloc: a walker could not reach its window");
+    BatchDev bd{};
+    bd.runs = s.desc;
+    bd.sweep = s.sweep;
+    bd.win = s.win;
+    bd.pair = s.pair;
+    bd.n_runs = 1;
+    bd.n_sweep = (int)nw;
+    bd.n_win = (int)h;
+    bd.n_pair = (int)(h / 2);
+    bd.P = 1;
+    bd.max_N = g.N;
+    bd.max_W = g.Wmax;
+    bd.j_words = (int)j_words;
+    bd.region = (int)sweep_region(g.Wmax, g.N, kWave);
+    for (int64_t r = 0; r < rounds; ++r) {
+        rc = rewl_launch_round(bd, stream, nullptr, nullptr);
+        if (rc) return fail(rc == -1 ? REWL_EINVAL : REWL_EDEVICE, "rewl_run_noalloc: round launch");
+    }
+    return REWL_OK;
+}
 // ------------------------------------------------------------------- server
 }  // extern "C"
 

@@ -166,6 +166,32 @@ inline size_t persist_lds_bytes(int P, int waves, int W, int N, int j_words)
     return (size_t)waves * P * sweep_region(W, N, kWave / P) + (size_t)j_words * 4 * (size_t)N;
 }
 
+// The allocation-free entry point (rewl_run_noalloc) keeps everything a run
+// needs besides the caller's output arrays in one static device array of
+// kNoAllocScratch bytes per device; its windows are passed to the set-up
+// kernel by value, so at most kNoAllocMaxWindows of them.
+constexpr size_t kNoAllocScratch = 128 * 1024;
+constexpr int kNoAllocMaxWindows = 64;
+
+struct NoAllocSetup {
+    RunDesc d;             // the run: outputs in the caller's arrays, the rest in the scratch
+    RunDesc *desc;         // launch tables in the scratch
+    SweepItem *sweep;
+    WinItem *win;
+    WinItem *pair;
+    const int8_t *J_raw;   // the couplings as given (bonds per site x N), in the scratch
+    double lnf_init;
+    int lo[kNoAllocMaxWindows], hi[kNoAllocMaxWindows];
+};
+
+// device address of the static scratch on the current device (looked up once
+// per device), or an error code
+int rewl_noalloc_scratch(void **ptr);
+// fills the run's state and the launch tables (no memset, no host copies of
+// tables): ln g and H zero, counters zero, ln f = lnf_init, unfinished
+// windows, couplings packed per site, one sweep item per walker
+int rewl_launch_noalloc_setup(const NoAllocSetup &s, void *stream);
+
 // launchers (rewl_kernels.hip); a launcher that returns -3 leaves the failed
 // HIP call and its error in rewl_launch_error() (per thread)
 const char *rewl_launch_error(void);

@@ -1138,6 +1138,73 @@ __global__ __launch_bounds__(kWave * kPersistMaxWaves) void persist_kernel(Batch
     }
 }
 
+// ----------------------------------------------- allocation-free entry point
+// The static device array behind rewl_run_noalloc.  Host code never passes its
+// name to a kernel (in host code the name is not a device address): it looks
+// the address up with hipGetSymbolAddress once per device and uses that.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+// Set-up of an allocation-free run: grid-stride loops over the caller's ln g
+// and H arrays (zero) and the run's bookkeeping in the scratch; block 0 also
+// writes the launch tables and packs the couplings (EA: right, left, down, up
+// per site; EA3: +x, -x, +y, -y | +z, -z, one int8 each).
+__global__ __launch_bounds__(256) void noalloc_setup_kernel(NoAllocSetup s)
+{
+    const RunDesc &a = s.d;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nthr = (size_t)gridDim.x * blockDim.x;
+    const size_t cells = (size_t)a.nw * (size_t)a.Wmax;
+    for (size_t i = tid; i < cells; i += nthr) {
+        a.lng[i] = 0.0;
+        a.H[i] = 0u;
+    }
+    for (size_t w = tid; w < (size_t)a.nw; w += nthr) {
+        a.t[w] = 0ull;
+        a.flat[w] = 0;
+        a.n_acc[w] = 0ull;
+        s.sweep[w] = SweepItem{0, (int)w, 1, 0};
+    }
+    for (size_t k = tid; k < (size_t)a.h; k += nthr) {
+        a.lnf[k] = s.lnf_init;
+        a.done[k] = 0;
+        a.phase[k] = 0;
+        a.finish[k] = -1;
+        a.first[k] = -1;
+        a.lo[k] = s.lo[k];
+        a.hi[k] = s.hi[k];
+        a.ex_prop[k] = 0ull;
+        a.ex_acc[k] = 0ull;
+        s.win[k] = WinItem{0, (int)k};
+        if ((int)k < a.h / 2) s.pair[k] = WinItem{0, (int)k};
+    }
+    const int L = a.L, N = a.N;
+    const uint8_t *J = reinterpret_cast<const uint8_t *>(s.J_raw);
+    if (a.model == kEA) {
+        for (size_t i = tid; i < (size_t)N; i += nthr) {
+            const int ii = (int)i, r = ii / L, c = ii % L;
+            const int lf = r * L + (c + L - 1) % L, up = ((r + L - 1) % L) * L + c;
+            a.J4[i] = (uint32_t)J[2 * ii] | ((uint32_t)J[2 * lf] << 8) |
+                      ((uint32_t)J[2 * ii + 1] << 16) | ((uint32_t)J[2 * up + 1] << 24);
+        }
+    } else if (a.model == kEA3) {
+        const int L2 = L * L;
+        for (size_t i = tid; i < (size_t)N; i += nthr) {
+            const int ii = (int)i, x = ii % L, y = (ii / L) % L, z = ii / L2;
+            const int xm = ii - x + (x + L - 1) % L;
+            const int ym = z * L2 + ((y + L - 1) % L) * L + x;
+            const int zm = ((z + L - 1) % L) * L2 + y * L + x;
+            a.J4[2 * i] = (uint32_t)J[3 * ii] | ((uint32_t)J[3 * xm] << 8) |
+                          ((uint32_t)J[3 * ii + 1] << 16) | ((uint32_t)J[3 * ym + 1] << 24);
+            a.J4[2 * i + 1] = (uint32_t)J[3 * ii + 2] | ((uint32_t)J[3 * zm + 2] << 8);
+        }
+    }
+    if (tid == 0) {
+        s.desc[0] = a;
+        *a.round = 0;
+        *a.status = 0;
+    }
+}
+
 // per run: 1 when every window is done
 __global__ void status_kernel(BatchDev bd, int *out)
 {
@@ -1282,6 +1349,30 @@ int rewl_launch_persist(const BatchDev &b, long long rounds, void *stream, void 
 }
 
 const char *rewl_launch_error(void) { return g_launch_err; }
+
+int rewl_noalloc_scratch(void **ptr)
+{
+    static std::atomic<void *> addr[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -3;
+    void *p = addr[dev].load();
+    if (!p) {
+        // with this device current: the array's address on this device
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return launch_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return -3;
+        addr[dev].store(p);
+    }
+    *ptr = p;
+    return 0;
+}
+
+int rewl_launch_noalloc_setup(const NoAllocSetup &s, void *stream)
+{
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3(64), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), s);
+    return launch_status("noalloc_setup_kernel launch");
+}
 
 int rewl_launch_init(const RunDesc &a, void *stream)
 {
