@@ -113,8 +113,6 @@ struct alignas(16) Prop {
                        // in bytes of the LDS ln g array
     uint32_t sp_off;   // LDS byte offset of the site's spin
     uint32_t flags;    // new state (8 bits) | old state << 8 | Potts r1 << 16
-                       // | 1 << 31 if an earlier proposal of the block touches
-                       //   the site or one of its neighbours
     uint32_t site;     // the site (unused by the pass; pads to 32 bytes)
 };
 

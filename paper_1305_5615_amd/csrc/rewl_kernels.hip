@@ -230,7 +230,8 @@ __global__ __launch_bounds__(256) void init_kernel(RunDesc a)
 // computes its energy change against the configuration at the start of the
 // block, and flags it when an earlier proposal of the block hits its site or a
 // neighbour (per-site masks in LDS, set with an atomic OR).  Every lane of the
-// group then applies the G attempts in order, identically; a flagged attempt
+// group then applies the G attempts in order, identically; an attempt whose
+// site or neighbour was changed by an earlier accepted move of the block
 // recomputes its energy change from the current spins, every other one uses
 // the precomputed value, so the result is that of the plain sequential walk.
 template <int MODEL>
@@ -484,7 +485,9 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
     for (long long base = 0; base < S; base += G) {
         const int n = (S - base < G) ? (int)(S - base) : G;
         const bool active = live && gl < n;
-        bool flagged = false;
+        // earlier attempts of the block that touched this attempt's site or a
+        // neighbour (one bit per lane of the group)
+        uint64_t earlier = 0;
         uint32_t post = 0;
         // state-dependent part, against the configuration at the block start
         if (active) {
@@ -500,11 +503,10 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
             p.lnf = one_over_t ? Wd / (double)(t0 + (unsigned long long)base + gl + 1) : lnf;
             p.d_addr = dE * ADDR_PER_E;
             p.sp_off = sp_base + (uint32_t)cur.site;
-            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (cur.r1 << 16) |
-                      ((seen & (bit - 1ull)) ? 0x80000000u : 0u);
+            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (cur.r1 << 16);
             p.site = (uint32_t)cur.site;
             stage[gl] = p;
-            flagged = (seen & (bit - 1ull)) != 0;
+            earlier = seen & (bit - 1ull);
         } else {
             // records past the last attempt: a zero move, read ahead only
             stage[gl] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
@@ -522,13 +524,16 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
 #pragma unroll
             for (int piece = 0; piece < 8; ++piece) draw_piece(nxt, piece);
         }
-        // flagged attempts of the block, one bit per lane (wave-uniform)
-        const uint64_t fmask = __builtin_amdgcn_ballot_w64(flagged);
+        // Attempts whose energy change must be recomputed, one bit per lane
+        // (wave-uniform): those for which an earlier attempt of the block that
+        // touched their site or a neighbour has been accepted.  Filled in as
+        // the pass accepts moves; only those moves change spins.
+        uint64_t pending = 0;
         if (live) {
             // In-order pass, executed identically by every lane of the group.
             // The only branch is taken when some group of the wave has a
-            // flagged attempt at this position; it is wave-uniform (a scalar
-            // test of the ballot), so unflagged positions cost no exec-mask
+            // pending attempt at this position; it is wave-uniform (a scalar
+            // test of `pending`), so other positions cost no exec-mask
             // changes.  As soon as an attempt is decided, the ln g at the next
             // attempt's target is loaded, ahead of the current bin's write-back
             // (so the LDS round trip overlaps that work), and the written
@@ -562,9 +567,9 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                 int nw = (int)(int8_t)(r0.flags & 0xFFu);
                 int old = (int)(int8_t)((r0.flags >> 8) & 0xFFu);
                 double gn = pick(d == 0, gcur, gnx);
-                if (__builtin_expect((fmask & (kFirstLanes<G>::value << j)) != 0, 0)) {
-                    // some group's attempt j is flagged: every group recomputes
-                    // from its current spins, the flagged ones keep the result.
+                if (__builtin_expect((pending & (kFirstLanes<G>::value << j)) != 0, 0)) {
+                    // some group's attempt j is pending: every group recomputes
+                    // from its current spins, the pending ones keep the result.
                     // The ln g of every bin one move can reach is loaded
                     // together with the spins (one LDS round trip, not two);
                     // with one walker per wave the neighbours come from the
@@ -599,7 +604,7 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                     } else {
                         g2 = ld(baddr + (uint32_t)d2);
                     }
-                    const bool f = (r0.flags & 0x80000000u) != 0;
+                    const bool f = ((pending >> ((lane & ~(G - 1)) + j)) & 1ull) != 0;
                     old = f ? o2 : old;
                     nw = f ? n2 : nw;
                     d = f ? d2 : d;
@@ -608,6 +613,10 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                 // outside the window the target holds +inf: gcur - gn = -inf
                 // never exceeds ln u, so the move is rejected
                 const bool accept = gcur - gn > r0.thr;
+                // an accepted move makes the later attempts that touch its site
+                // or a neighbour pending (their lanes' `earlier` has bit j)
+                pending |= __builtin_amdgcn_ballot_w64(((earlier >> j) & 1ull) != 0) &
+                           __builtin_amdgcn_ballot_w64(accept);
                 baddr = accept ? baddr + (uint32_t)d : baddr;
                 const double gsel = pick(accept, gn, gcur);
                 gnx = ld(baddr + (uint32_t)r1.d);
