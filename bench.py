@@ -467,18 +467,61 @@ def errors(rewl, args):
     print(json.dumps(out), flush=True)
 
 
+def accuracy(rewl, args):
+    """One run of a workload to convergence (possibly over several invocations:
+    it checkpoints after --max-rounds rounds and --resume continues), then max
+    |ln g - ln g_exact| where an exact DOS is stored.  Walkers per window and
+    the ln f schedule may differ from the workload's (--accuracy-m, --schedule,
+    --lnf-final)."""
+    from workloads import run_params
+
+    p = run_params(args.workload, seed=1)
+    over = {"schedule": args.schedule}
+    if args.accuracy_m:
+        over["walkers_per_window"] = args.accuracy_m
+    if args.lnf_final:
+        over["lnf_final"] = args.lnf_final
+    p.update(over)
+    t0 = time.perf_counter()
+    r = rewl.Run.load(args.resume) if args.resume else rewl.Run(**run_kwargs(p))
+    issued, ok, rounds = 0, False, 0
+    while issued < args.max_rounds and not ok:
+        n = min(20_000, args.max_rounds - issued)
+        ok, rounds = r.run(n)
+        issued += n
+        ws = r.windows()
+        log(f"{time.perf_counter() - t0:.0f} s: rounds {r.info()['rounds']}, windows done "
+            f"{sum(w['done'] for w in ws)}/{len(ws)}, largest ln f {max(w['lnf'] for w in ws):.3g}")
+    out = {"metric": "max |ln g - ln g_exact| of one run to convergence",
+           "workload": WORKLOAD_TEXT[args.workload], "overrides": over,
+           "seconds_this_invocation": time.perf_counter() - t0, "converged": ok}
+    if ok:
+        out["rounds"] = rounds
+        out["max_abs_dlng_vs_exact"] = exact_error(p, r.lng())
+    else:
+        r.save(args.checkpoint)
+        out["checkpoint"] = args.checkpoint
+        out["rounds_so_far"] = r.info()["rounds"]
+    r.close()
+    print(json.dumps(out), flush=True)
+
+
 def calibrate_copy(mb):
     """One device-to-device copy of `mb` MiB (read mb, write mb) for scaling
-    the FETCH_SIZE / WRITE_SIZE counters; use a copy several times larger than
-    the 256 MB last-level cache so that its reads come from HBM."""
+    the FETCH_SIZE / WRITE_SIZE counters.  The source is written first and then
+    pushed out of the last-level cache (256 MB) by writing 1 GiB elsewhere, so
+    the copy's reads come from HBM; use a copy several times larger than that
+    cache."""
     import torch
 
     src = torch.ones(mb << 18, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    flush.fill_(2.0)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"copy: {mb} MiB read, {mb} MiB written")
+    log(f"copy: {mb} MiB read, {mb} MiB written (after a 1 GiB fill)")
 
 
 
@@ -660,6 +703,18 @@ def main():
                          "setting")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="counter calibration: one device copy of this many MiB")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="accuracy mode: one run of --workload to convergence (checkpointed "
+                         "after --max-rounds rounds; --resume continues) and its max |d ln g|")
+    ap.add_argument("--accuracy-m", type=int, default=0,
+                    help="accuracy mode: walkers per window (0: the workload's)")
+    ap.add_argument("--schedule", default="halving", choices=("halving", "1/t"),
+                    help="accuracy mode: ln f schedule")
+    ap.add_argument("--lnf-final", type=float, default=0.0,
+                    help="accuracy mode: ln f_final (0: the workload's)")
+    ap.add_argument("--resume", default="", help="accuracy mode: checkpoint to continue from")
+    ap.add_argument("--checkpoint", default="gpurun_out/accuracy.rewl",
+                    help="accuracy mode: where to write the checkpoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: each REWL run lives on one device and "
@@ -688,6 +743,9 @@ def main():
         return
     if args.errors > 1:
         errors(rewl, args)
+        return
+    if args.accuracy:
+        accuracy(rewl, args)
         return
 
     budget = Budget(args.budget)

@@ -112,8 +112,8 @@ struct alignas(16) Prop {
     int32_t d_addr;    // energy change against the block-start configuration,
                        // in bytes of the LDS ln g array
     uint32_t sp_off;   // LDS byte offset of the site's spin
-    uint32_t flags;    // new state (8 bits) | old state << 8 | Potts r1 << 16
-    uint32_t site;     // the site (unused by the pass; pads to 32 bytes)
+    uint32_t flags;    // new state (8 bits) | Potts r1 << 16
+    uint32_t old;      // old state (8 bits)
 };
 
 // LDS bytes one walker needs in the sweep with G = 64 / P attempts per block:

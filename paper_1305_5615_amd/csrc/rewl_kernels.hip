@@ -380,13 +380,33 @@ __device__ __forceinline__ void walker_store(const RunDesc &a, const WalkerLds<G
     for (int i = gl; i < (a.N + 3) / 4; i += G) dst[i] = src[i];
 }
 
+// LDS byte address of a pointer into the work-group's shared memory, and
+// loads / stores at such an address: the in-order pass carries addresses, so
+// its loads need no base added
+using lds_u8 = __attribute__((address_space(3))) unsigned char;
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const lds_u8 *)p;
+}
+__device__ __forceinline__ double lds_ld_f64(uint32_t addr)
+{
+    return *(const __attribute__((address_space(3))) double *)(uintptr_t)addr;
+}
+__device__ __forceinline__ void lds_st_f64(uint32_t addr, double v)
+{
+    *(__attribute__((address_space(3))) double *)(uintptr_t)addr = v;
+}
+__device__ __forceinline__ void lds_st_u8(uint32_t addr, unsigned char v)
+{
+    *(lds_u8 *)(uintptr_t)addr = v;
+}
+
 // the two proposals past the last of a block, read ahead by the in-order
 // pass: zero moves
 template <int G>
-__device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, const unsigned char *wbase,
-                                             int gl)
+__device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, int gl)
 {
-    const uint32_t sp_base = (uint32_t)(reinterpret_cast<const unsigned char *>(L.sp) - wbase);
+    const uint32_t sp_base = lds_addr(L.sp);
     for (int i = gl; i < 2; i += G) L.stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
 }
 
@@ -397,14 +417,13 @@ __device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, const unsign
 // wave per CU, so the launcher picks it by the number of waves.
 //
 // S attempts of the walker of this lane's group (standard-WL paragraph), its
-// state in LDS at L; wbase is the start of the wave's LDS regions, against
-// which the pass addresses ln g and the spins.  live: the walker exists and its
+// state in LDS at L.  live: the walker exists and its
 // window is running (a group that is not live only keeps the wave's lanes in
 // step).  Returns the walker's bin after the attempts (window-local) and adds
 // its accepted moves to acc.
 template <int MODEL, int P, bool RP>
-__device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *wbase,
-                                              const WalkerLds<kWave / P> &L, const uint32_t *J_s,
+__device__ __forceinline__ int sweep_attempts(const RunDesc &a, const WalkerLds<kWave / P> &L,
+                                              const uint32_t *J_s,
                                               int w, bool live, int W, int b0, double lnf,
                                               bool one_over_t, unsigned long long t0,
                                               unsigned int &acc)
@@ -423,8 +442,8 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
     uint32_t *post_s = L.post;
     TagT *tag = L.tag;
     int8_t *sp = L.sp;
-    const uint32_t sp_base = (uint32_t)(reinterpret_cast<unsigned char *>(sp) - wbase);
-    const uint32_t lng_base = (uint32_t)(reinterpret_cast<unsigned char *>(lng_s) - wbase);
+    const uint32_t sp_base = lds_addr(sp);
+    const uint32_t lng_base = lds_addr(lng_s);
 
     // the 1/t rule: ln f = W / t after each attempt, t = attempts made so far
     const double Wd = (double)W;
@@ -503,8 +522,8 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
             p.lnf = one_over_t ? Wd / (double)(t0 + (unsigned long long)base + gl + 1) : lnf;
             p.d_addr = dE * ADDR_PER_E;
             p.sp_off = sp_base + (uint32_t)cur.site;
-            p.flags = ((uint32_t)nw & 0xFFu) | (((uint32_t)old & 0xFFu) << 8) | (cur.r1 << 16);
-            p.site = (uint32_t)cur.site;
+            p.flags = ((uint32_t)nw & 0xFFu) | (cur.r1 << 16);
+            p.old = (uint32_t)old & 0xFFu;
             stage[gl] = p;
             earlier = seen & (bit - 1ull);
         } else {
@@ -534,14 +553,15 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
             // The only branch is taken when some group of the wave has a
             // pending attempt at this position; it is wave-uniform (a scalar
             // test of `pending`), so other positions cost no exec-mask
-            // changes.  As soon as an attempt is decided, the ln g at the next
-            // attempt's target is loaded, ahead of the current bin's write-back
-            // (so the LDS round trip overlaps that work), and the written
-            // value is forwarded when the next target is the current bin.
+            // changes.  As soon as an attempt is decided the current bin's
+            // ln g is written back and the ln g at the next attempt's target is
+            // loaded (after the write, which a wave's in-order LDS accesses
+            // make visible to it, so a target equal to the current bin needs no
+            // forwarding); the spin store and the bookkeeping follow.
             struct Rec {
                 double thr, lnf;
                 int d;
-                uint32_t sp_off, flags;
+                uint32_t sp_off, flags, old;
             };
             auto fetch = [&](int j) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(&stage[j]);
@@ -552,21 +572,19 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                 f.d = (int)u.x;
                 f.sp_off = u.y;
                 f.flags = u.z;
+                f.old = u.w;
                 return f;
             };
-            auto ld = [&](uint32_t addr) {
-                return *reinterpret_cast<const double *>(wbase + addr);
-            };
+            auto ld = [&](uint32_t addr) { return lds_ld_f64(addr); };
             Rec r0 = fetch(0), r1 = fetch(1);
-            // ln g at the next attempt's target, loaded before the current
-            // bin's ln g is written back (forwarded when the target is that bin)
+            // ln g at the first attempt's target
             double gnx = ld(baddr + (uint32_t)r0.d);
             auto step = [&](int j) {
                 const Rec r2 = fetch(j + 2);
                 int d = r0.d;
-                int nw = (int)(int8_t)(r0.flags & 0xFFu);
-                int old = (int)(int8_t)((r0.flags >> 8) & 0xFFu);
-                double gn = pick(d == 0, gcur, gnx);
+                // the spin store takes the low byte of these words
+                uint32_t nw = r0.flags, old = r0.old;
+                double gn = gnx;
                 if (__builtin_expect((pending & (kFirstLanes<G>::value << j)) != 0, 0)) {
                     // some group's attempt j is pending: every group recomputes
                     // from its current spins, the pending ones keep the result.
@@ -595,6 +613,7 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                     }
                     const int o2 = sp[s];
                     const int n2 = new_state<MODEL>(o2, (r0.flags >> 16) & 0x7Fu, q);
+                    const uint32_t o2w = (uint32_t)o2 & 0xFFu, n2w = (uint32_t)n2 & 0xFFu;
                     const int d2 = delta_e<MODEL>(sp, J_s, s, nb, o2, n2) * ADDR_PER_E;
                     double g2;
                     if (kCandidates<MODEL>::value) {
@@ -605,8 +624,8 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                         g2 = ld(baddr + (uint32_t)d2);
                     }
                     const bool f = ((pending >> ((lane & ~(G - 1)) + j)) & 1ull) != 0;
-                    old = f ? o2 : old;
-                    nw = f ? n2 : nw;
+                    old = f ? o2w : old;
+                    nw = f ? n2w : nw;
                     d = f ? d2 : d;
                     gn = pick(f, g2, gn);
                 }
@@ -619,10 +638,10 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, unsigned char *w
                            __builtin_amdgcn_ballot_w64(accept);
                 baddr = accept ? baddr + (uint32_t)d : baddr;
                 const double gsel = pick(accept, gn, gcur);
-                gnx = ld(baddr + (uint32_t)r1.d);
                 gcur = gsel + r0.lnf;
-                *reinterpret_cast<double *>(wbase + baddr) = gcur;
-                wbase[r0.sp_off] = (unsigned char)(int8_t)(accept ? nw : old);
+                lds_st_f64(baddr, gcur);
+                gnx = ld(baddr + (uint32_t)r1.d);
+                lds_st_u8(r0.sp_off, (unsigned char)(accept ? nw : old));
                 // bin after attempt j and its acceptance, for lane j's H update
                 if constexpr (RP)
                     post = (gl == j) ? (baddr | (accept ? 1u : 0u)) : post;
@@ -679,7 +698,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const int lo = live ? a.lo[k] : 0;
     const int W = live ? a.hi[k] - lo + 1 : 1;
     if (live) walker_load<G>(a, L, w, W, gl);
-    stage_guards<G>(L, smem, gl);
+    stage_guards<G>(L, gl);
     constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);  // coupling words per site
     for (int i = lane; i < JW * N; i += kWave) J_s[i] = a.J4[i];
     __syncthreads();
@@ -690,8 +709,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const unsigned long long t0 = live ? a.t[w] : 0ull;
     const int b0 = live ? (a.E[w] - elo) / STEP : 0;
     unsigned int acc = 0;
-    const int b = sweep_attempts<MODEL, P, RP>(a, smem, L, J_s, w, live, W, b0, lnf, one_over_t,
-                                               t0, acc);
+    const int b = sweep_attempts<MODEL, P, RP>(a, L, J_s, w, live, W, b0, lnf, one_over_t, t0, acc);
     if (live) {
         walker_store<G>(a, L, w, W, gl);
         const unsigned int acc_w = group_sum<G>(acc);
@@ -942,7 +960,7 @@ __device__ __forceinline__ void persist_body(const RunDesc &a, const BatchDev &b
     const int elo = a.e_min + lo * STEP;
 
     if (exists) walker_load<G>(a, L, w, W, gl);
-    stage_guards<G>(L, wbase, gl);
+    stage_guards<G>(L, gl);
     constexpr int JW = (MODEL == kEA) ? 1 : (MODEL == kEA3 ? 2 : 0);
     for (int i = tid; i < JW * N; i += nthr) J_s[i] = a.J4[i];
     for (int i = tid; i < nw; i += nthr) {
@@ -985,7 +1003,7 @@ __device__ __forceinline__ void persist_body(const RunDesc &a, const BatchDev &b
             const unsigned long long t0 = exists ? ps.t[w] : 0ull;
             const int b0 = exists ? (ps.E[w] - elo) / STEP : 0;
             unsigned int acc = 0;
-            const int b = sweep_attempts<MODEL, P, RP>(a, wbase, L, J_s, w, live, W, b0,
+            const int b = sweep_attempts<MODEL, P, RP>(a, L, J_s, w, live, W, b0,
                                                        live ? ps.lnf[k] : 0.0,
                                                        live && ps.phase[k] != 0, t0, acc);
             acc_all += acc;
