@@ -2,7 +2,10 @@
 
 Flags: -ffp-contract=off keeps every floating-point expression a sequence of
 single IEEE operations (no fused multiply-add), -packed-fp32-ops off keeps the
-compiler from forming packed FP32 instructions.
+compiler from forming packed FP32 instructions, and the instruction-level-
+parallelism scheduling strategy orders each basic block for latency rather
+than register pressure: the sweep runs one wave per SIMD, so occupancy gains
+nothing and the in-order wave's stalls are what cost time.
 """
 from __future__ import annotations
 
@@ -27,6 +30,7 @@ def build(verbose=False):
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-amdgpu-sched-strategy=max-ilp",
            "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:

@@ -330,13 +330,13 @@ __device__ __forceinline__ WalkerLds<G> walker_lds(unsigned char *mine, int max_
 
 // Orders the LDS writes of a wave's lanes before the reads of other lanes of
 // the same wave.  A wave's LDS instructions execute in order, so this only has
-// to keep the compiler from moving accesses across it; other waves of the
-// work-group are not waited for.
+// to keep the compiler from moving accesses across it: a wave barrier, which
+// the compiler treats as touching memory and which emits no instruction.  No
+// memory fence, which would make the wave wait for all of its outstanding LDS
+// operations; other waves of the work-group are not waited for.
 __device__ __forceinline__ void wave_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // HBM -> LDS: a walker's ln g (guard bins of +inf on either side: a move that
