@@ -713,7 +713,7 @@ def main():
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="accuracy mode: ln f_final (0: the workload's)")
     ap.add_argument("--resume", default="", help="accuracy mode: checkpoint to continue from")
-    ap.add_argument("--checkpoint", default="gpurun_out/accuracy.rewl",
+    ap.add_argument("--checkpoint", default="accuracy.rewl",
                     help="accuracy mode: where to write the checkpoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
