@@ -497,13 +497,48 @@ def accuracy(rewl, args):
            "seconds_this_invocation": time.perf_counter() - t0, "converged": ok}
     if ok:
         out["rounds"] = rounds
-        out["max_abs_dlng_vs_exact"] = exact_error(p, r.lng())
+        lng = r.lng()
+        out["max_abs_dlng_vs_exact"] = exact_error(p, lng)
+        out["checks"] = dos_checks(p, r, lng)
     else:
         r.save(args.checkpoint)
         out["checkpoint"] = args.checkpoint
         out["rounds_so_far"] = r.info()["rounds"]
     r.close()
     print(json.dumps(out), flush=True)
+
+
+def dos_checks(p, r, lng):
+    """Checks of a converged ln g that need no exact DOS: the log of the total
+    number of states against N ln(states per site), and the peak of the
+    specific heat per site C/N = beta^2 var(E) / N on a temperature scan (for
+    first-order transitions a known finite-size law places it)."""
+    import numpy as np
+
+    n, states = r.N, (p.get("q") or 2) if p["model"] == "potts" else 2
+    E = r.energies().astype(float)
+    fin = np.isfinite(lng)
+    E, g = E[fin], lng[fin]
+    m = g.max()
+    out = {"log_total_states": float(m + math.log(np.exp(g - m).sum())),
+           "n_ln_states_per_site": n * math.log(states)}
+
+    def heat(T):
+        w = g - E / T
+        wm = w.max()
+        pr = np.exp(w - wm)
+        z = pr.sum()
+        e1 = (pr * E).sum() / z
+        return ((pr * E * E).sum() / z - e1 * e1) / (T * T) / n
+
+    Ts = np.linspace(0.2, 5.0, 4801)
+    cs = np.array([heat(T) for T in Ts])
+    i = int(cs.argmax())
+    fine = np.linspace(Ts[max(i - 1, 0)], Ts[min(i + 1, len(Ts) - 1)], 2001)
+    cf = np.array([heat(T) for T in fine])
+    j = int(cf.argmax())
+    out["specific_heat_peak"] = {"T": float(fine[j]), "C_per_site": float(cf[j])}
+    return out
 
 
 def calibrate_copy(mb):

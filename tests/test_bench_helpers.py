@@ -124,3 +124,34 @@ def test_roofline_arithmetic():
     assert r["bound"] == "alu" and r["unit"] == "TOP/s" and r["traffic"] == 123.0
     assert abs(r["frac_at_recount"] - r["frac"] * 200 / 170) < 1e-12
     assert bench.roofline(attempts=1, launches=0, launch_ms=0.0, traffic=None, kernel="k") is None
+
+
+def test_dos_checks_on_the_exact_ising_density_of_states():
+    """The accuracy mode's checks that need no exact DOS, applied to the exact
+    8x8 Ising DOS: the total count is 2^N exactly, and the specific heat peaks
+    above the infinite-lattice T_c = 2/ln(1+sqrt 2) (finite-size shift of the
+    8x8 torus) with the value a direct evaluation gives there."""
+    import math
+
+    import bench
+
+    E, ref = load_ising_golden(8)
+
+    class R:
+        N = 64
+
+        def energies(self):
+            return np.asarray(E)
+
+    out = bench.dos_checks({"model": "ising", "L": 8}, R(), ref)
+    assert abs(out["log_total_states"] - 64 * math.log(2)) < 1e-9
+    assert out["n_ln_states_per_site"] == 64 * math.log(2)
+    T = out["specific_heat_peak"]["T"]
+    assert 2 / math.log(1 + math.sqrt(2)) < T < 2.6
+    fin = np.isfinite(ref)
+    e, g = np.asarray(E, dtype=float)[fin], ref[fin]
+    w = g - e / T
+    pr = np.exp(w - w.max())
+    mean = (pr * e).sum() / pr.sum()
+    var = (pr * (e - mean) ** 2).sum() / pr.sum()
+    assert abs(out["specific_heat_peak"]["C_per_site"] - var / T ** 2 / 64) < 1e-9
