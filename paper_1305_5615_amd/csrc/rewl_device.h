@@ -23,8 +23,9 @@ __device__ __forceinline__ void philox_rounds(U4 &c, uint32_t &k0, uint32_t &k1,
     for (int r = r0; r < r1; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        // three-input XOR in one instruction (bitop3 truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96);
         c.y = (uint32_t)p1;
         c.w = (uint32_t)p0;
         c.x = n0;
