@@ -119,6 +119,25 @@ static const double LN2_HI = 0x1.62e42ffp-1;        /* round(ln2 * 2^32) / 2^32 
 static const double LN2_LO = -0x1.718432a1b0e26p-35; /* RN(ln2 - LN2_HI) */
 static const double SQRT2 = 0x1.6a09e667f3bcdp+0;  /* RN(sqrt 2) */
 
+/* One Horner step of ln u's series, Q z + c rounded once (a fused multiply-add,
+ * C99 fma).  Where the host has the FMA instructions the step is compiled to
+ * one of them; elsewhere libm's fma gives the same, correctly rounded, value. */
+#if defined(__x86_64__) && defined(__GNUC__)
+__attribute__((target("fma"))) static double horner_hw(double Q, double z, double c)
+{
+    return __builtin_fma(Q, z, c);
+}
+static double horner_sw(double Q, double z, double c) { return fma(Q, z, c); }
+static int have_fma = -1;
+static double horner(double Q, double z, double c)
+{
+    if (have_fma < 0) have_fma = __builtin_cpu_supports("fma") ? 1 : 0;
+    return have_fma ? horner_hw(Q, z, c) : horner_sw(Q, z, c);
+}
+#else
+static double horner(double Q, double z, double c) { return fma(Q, z, c); }
+#endif
+
 double orc_ln_u(double u)
 {
     int e;
@@ -131,11 +150,12 @@ double orc_ln_u(double u)
     }
     double s = (f - 1.0) / (f + 1.0);
     double z = s * s;
-    /* Horner over c_i = RN(1/(2i+1)), i = 11 .. 1; the leading term 1 is added
-     * last, as s + s z Q(z), to keep the rounding error near one ulp */
+    /* Horner over c_i = RN(1/(2i+1)), i = 11 .. 1, each step one fused
+     * multiply-add; the leading term 1 is added last, as s + s z Q(z), to keep
+     * the rounding error near one ulp */
     double Q = 1.0 / 23.0;
     for (int i = 10; i >= 1; --i)
-        Q = Q * z + 1.0 / (double)(2 * i + 1);
+        Q = horner(Q, z, 1.0 / (double)(2 * i + 1));
     double ed = (double)e;
     double lnf = (s + s * (z * Q)) * 2.0;
     return ed * LN2_HI + (ed * LN2_LO + lnf);

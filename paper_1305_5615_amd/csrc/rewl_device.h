@@ -54,7 +54,8 @@ __device__ __forceinline__ uint32_t mulhi32(uint32_t word, uint32_t n)
 // n = 2k+1 < 2^53 is written as f 2^msb with f in [1, 2) directly from its
 // bits, f is folded into [sqrt2/2, sqrt2], and ln f = 2 atanh(s) with
 // s = (f-1)/(f+1) is summed as 2 (s + s z Q(z)), z = s^2,
-// Q(z) = 1/3 + z/5 + ... + z^10/23 (coefficients RN(1/(2i+1))).  ln 2 enters
+// Q(z) = 1/3 + z/5 + ... + z^10/23 (coefficients RN(1/(2i+1)), Horner with
+// fused multiply-adds).  ln 2 enters
 // split as LN2_HI (32 fractional bits, so e * LN2_HI is exact) + LN2_LO.
 // Two halves, so that a caller can interleave them with other work:
 // ln_u_reduce gives s, z = s^2 and the exponent e, ln_u_sum the result.
@@ -88,17 +89,18 @@ __device__ __forceinline__ double ln_u_sum(const LnU &a)
     const double kLn2Hi = 0x1.62e42ffp-1;
     const double kLn2Lo = -0x1.718432a1b0e26p-35;
     const double z = a.z, s = a.s;
+    // Horner, each step one fused multiply-add (a single rounding)
     double Q = 1.0 / 23.0;
-    Q = Q * z + 1.0 / 21.0;
-    Q = Q * z + 1.0 / 19.0;
-    Q = Q * z + 1.0 / 17.0;
-    Q = Q * z + 1.0 / 15.0;
-    Q = Q * z + 1.0 / 13.0;
-    Q = Q * z + 1.0 / 11.0;
-    Q = Q * z + 1.0 / 9.0;
-    Q = Q * z + 1.0 / 7.0;
-    Q = Q * z + 1.0 / 5.0;
-    Q = Q * z + 1.0 / 3.0;
+    Q = __fma_rn(Q, z, 1.0 / 21.0);
+    Q = __fma_rn(Q, z, 1.0 / 19.0);
+    Q = __fma_rn(Q, z, 1.0 / 17.0);
+    Q = __fma_rn(Q, z, 1.0 / 15.0);
+    Q = __fma_rn(Q, z, 1.0 / 13.0);
+    Q = __fma_rn(Q, z, 1.0 / 11.0);
+    Q = __fma_rn(Q, z, 1.0 / 9.0);
+    Q = __fma_rn(Q, z, 1.0 / 7.0);
+    Q = __fma_rn(Q, z, 1.0 / 5.0);
+    Q = __fma_rn(Q, z, 1.0 / 3.0);
     const double ed = (double)a.e;
     const double lnf = (s + s * (z * Q)) * 2.0;
     return ed * kLn2Hi + (ed * kLn2Lo + lnf);

@@ -43,8 +43,8 @@ MUTATIONS = {
         "uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;",
         "uint64_t p0 = (uint64_t)0xD2511F55u * (uint64_t)c0;", "philox_matches_rocrand"),
     "the ln u series shifted by one term": (
-        "Q = Q * z + 1.0 / (double)(2 * i + 1);",
-        "Q = Q * z + 1.0 / (double)(2 * i + 3);", "ln_u_accuracy"),
+        "Q = horner(Q, z, 1.0 / (double)(2 * i + 1));",
+        "Q = horner(Q, z, 1.0 / (double)(2 * i + 3));", "ln_u_accuracy"),
     "the joining point one bin late": (
         "if (diff < best_diff) { best_diff = diff; best = prev; }",
         "if (diff < best_diff) { best_diff = diff; best = b; }",
