@@ -285,6 +285,14 @@ template <int MODEL> struct kCandidates {
     static constexpr bool value = MODEL != kPotts;
 };
 
+// sum over the G aligned lanes of a walker group
+template <int G>
+__device__ __forceinline__ unsigned int group_sum(unsigned int v)
+{
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // guard bins on either side of a window's ln g: the largest single-site
 // energy change is 8 (Ising, +-J: 2 bins of 4) or 4 (Potts: 4 bins of 1)
 constexpr int kGuard = 4;
@@ -402,8 +410,8 @@ __device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, int gl)
     for (int i = gl; i < 2; i += G) L.stage[G + i] = Prop{0.0, 0.0, 0, sp_base, 0u, 0u};
 }
 
-// RP: the per-step bin records (the bin after each attempt, for the H update
-// at the end of a block) are kept in a register of the lane that drew the attempt rather
+// RP: the per-step bin records (bin | accepted, for the H update at the end
+// of a block) are kept in a register of the lane that drew the attempt rather
 // than stored to LDS.  That costs VALU work per step and saves an LDS store;
 // it measured faster when several waves share a CU's LDS and slower with one
 // wave per CU, so the launcher picks it by the number of waves.
@@ -412,7 +420,7 @@ __device__ __forceinline__ void stage_guards(const WalkerLds<G> &L, int gl)
 // state in LDS at L.  live: the walker exists and its
 // window is running (a group that is not live only keeps the wave's lanes in
 // step).  Returns the walker's bin after the attempts (window-local) and adds
-// the walker's accepted moves to acc, in every lane of its group.
+// its accepted moves to acc.
 template <int MODEL, int P, bool RP>
 __device__ __forceinline__ int sweep_attempts(const RunDesc &a, const WalkerLds<kWave / P> &L,
                                               const uint32_t *J_s,
@@ -624,7 +632,6 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, const WalkerLds<
                 // outside the window the target holds +inf: gcur - gn = -inf
                 // never exceeds ln u, so the move is rejected
                 const bool accept = gcur - gn > r0.thr;
-                acc += accept ? 1u : 0u;
                 // an accepted move makes the later attempts that touch its site
                 // or a neighbour pending (their lanes' `earlier` has bit j)
                 pending |= __builtin_amdgcn_ballot_w64(((earlier >> j) & 1ull) != 0) &
@@ -635,11 +642,11 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, const WalkerLds<
                 lds_st_f64(baddr, gcur);
                 gnx = ld(baddr + (uint32_t)r1.d);
                 lds_st_u8(r0.sp_off, (unsigned char)(accept ? nw : old));
-                // bin after attempt j, for lane j's H update
+                // bin after attempt j and its acceptance, for lane j's H update
                 if constexpr (RP)
-                    post = (gl == j) ? baddr : post;
+                    post = (gl == j) ? (baddr | (accept ? 1u : 0u)) : post;
                 else
-                    post_s[j] = baddr;
+                    post_s[j] = baddr | (accept ? 1u : 0u);
                 r0 = r1;
                 r1 = r2;
             };
@@ -662,7 +669,8 @@ __device__ __forceinline__ int sweep_attempts(const RunDesc &a, const WalkerLds<
         // H of the block's attempts, one atomic per lane
         if (active) {
             const uint32_t v = RP ? post : post_s[gl];
-            atomicAdd(&H_s[(v - lng_base) >> 3], 1u);
+            atomicAdd(&H_s[((v & ~7u) - lng_base) >> 3], 1u);
+            acc += v & 1u;
         }
         // (a block shorter than G is the last one: its next draws are unused)
         cur = nxt.out;
@@ -704,7 +712,7 @@ __device__ __forceinline__ void sweep_body(const RunDesc &a, const SweepItem &it
     const int b = sweep_attempts<MODEL, P, RP>(a, L, J_s, w, live, W, b0, lnf, one_over_t, t0, acc);
     if (live) {
         walker_store<G>(a, L, w, W, gl);
-        const unsigned int acc_w = acc;
+        const unsigned int acc_w = group_sum<G>(acc);
         if (gl == 0) {
             a.E[w] = elo + b * STEP;
             a.t[w] = t0 + (unsigned long long)a.S;
@@ -1122,7 +1130,8 @@ __device__ __forceinline__ void persist_body(const RunDesc &a, const BatchDev &b
     // LDS -> HBM
     if (exists) {
         walker_store<G>(a, L, w, W, gl);
-        if (gl == 0) a.n_acc[w] += acc_all;
+        const unsigned int acc_w = group_sum<G>(acc_all);
+        if (gl == 0) a.n_acc[w] += acc_w;
     }
     for (int i = tid; i < nw; i += nthr) {
         a.E[i] = ps.E[i];
