@@ -35,8 +35,8 @@ from the package's autotuner unless given.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form auto|rounds|persistent]
                        [--walkers-per-wave P] [--legs all|headline] [--no-cpu]
 Other modes (one JSON line each): --rounds R (profile: fixed rounds of one
-workload), --served N, --balanced, --errors R, --copy-mb M (counter
-calibration).
+workload), --served N, --balanced, --errors R, --time-to-dos N, --copy-mb M
+(counter calibration).
 """
 from __future__ import annotations
 
@@ -584,26 +584,29 @@ def plain_rate(rewl, name, rounds):
             "sweep_avg_us": 1e3 * (ms - ms0) / max(n - n0, 1)}
 
 
-def time_to_dos_small(rewl, seeds, budget_plain_s):
-    """p50/p99 time-to-converged ln g of the 8x8 Ising workload: each seed as a
-    plain run, one after another (time from creation to the stitched ln g on
-    the host), and all seeds in one batch, launched as the autotuner picks and
-    polled every 16 rounds (time from the batch's creation to the run's
-    stitched ln g on the host)."""
+def time_to_dos(rewl, seeds, budget_plain_s, workload="ising8", max_rounds=100_000,
+                verbose=False):
+    """p50/p99 time-to-converged ln g of a workload: each seed as a plain run,
+    one after another (time from creation to the stitched ln g on the host),
+    and all seeds in one batch, launched as the autotuner picks and polled every
+    16 rounds (time from the batch's creation to the run's stitched ln g on
+    the host)."""
     import numpy as np
     import torch
 
     from paper_1305_5615_amd import autotune
     from workloads import run_params
 
-    params = [run_params("ising8", seed=s) for s in seeds]
+    params = [run_params(workload, seed=s) for s in seeds]
     plain, plain_err, plain_att = [], [], 0
     t_start = time.perf_counter()
     for p in params:
         if time.perf_counter() - t_start > budget_plain_s:
             log(f"time-to-DOS: plain runs stopped after {len(plain)} seeds (budget)")
             break
-        res = gpu_full_run(rewl, p, 100_000)
+        res = gpu_full_run(rewl, p, max_rounds)
+        if verbose:
+            log(f"time-to-DOS: plain {workload} seed {p['seed']}: {res['seconds']:.2f} s")
         plain.append(res["seconds"])
         plain_att += res["attempts"]
         plain_err.append(exact_error(p, res["lng"]))
@@ -617,7 +620,7 @@ def time_to_dos_small(rewl, seeds, budget_plain_s):
     done_at = [None] * len(params)
     errs = [None] * len(params)
     issued = 0
-    while issued < 100_000:
+    while issued < max_rounds:
         b.step(16)
         issued += 16
         d = b.done()
@@ -625,6 +628,8 @@ def time_to_dos_small(rewl, seeds, budget_plain_s):
             if done_at[i] is None:
                 lng = b[int(i)].lng()
                 done_at[i] = time.perf_counter() - t0
+                if verbose:
+                    log(f"time-to-DOS: batched run {int(i)} done at {done_at[i]:.2f} s")
                 errs[i] = exact_error(params[i], lng)
         if d.all():
             break
@@ -635,7 +640,7 @@ def time_to_dos_small(rewl, seeds, budget_plain_s):
     # the same requests all arriving at once and served one after another:
     # a run's time-to-DOS then includes waiting for the runs before it
     fifo = list(np.cumsum(plain))
-    return {"workload": WORKLOAD_TEXT["ising8"], "seeds": [int(s) for s in seeds],
+    return {"workload": WORKLOAD_TEXT[workload], "seeds": [int(s) for s in seeds],
             "plain_fifo": {"runs": len(fifo), "p50_s": percentile(fifo, 50),
                            "p99_s": percentile(fifo, 99)},
             "plain": {"runs": len(plain), "p50_s": percentile(plain, 50),
@@ -736,6 +741,9 @@ def main():
     ap.add_argument("--errors", type=int, default=0,
                     help="error-bar mode: this many independent runs per walkers-per-window "
                          "setting")
+    ap.add_argument("--time-to-dos", type=int, default=0,
+                    help="time-to-DOS mode: seeds 1..N of --workload as plain runs one after "
+                         "another (within --budget seconds) and all in one batch")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="counter calibration: one device copy of this many MiB")
     ap.add_argument("--accuracy", action="store_true",
@@ -781,6 +789,12 @@ def main():
         return
     if args.accuracy:
         accuracy(rewl, args)
+        return
+    if args.time_to_dos > 0:
+        out = time_to_dos(rewl, range(1, args.time_to_dos + 1), args.budget,
+                          workload=args.workload, max_rounds=args.max_rounds, verbose=True)
+        out["metric"] = "time-to-converged ln g, plain one after another vs batched"
+        print(json.dumps(out), flush=True)
         return
 
     budget = Budget(args.budget)
@@ -838,7 +852,7 @@ def main():
                 legs[f"plain_{name}"] = plain_rate(rewl, name, rounds)
                 log(f"plain {name}: {legs[f'plain_{name}']['attempts_per_s'] / 1e9:.3f} G/s")
         if budget.allows(45, "time-to-DOS"):
-            legs["time_to_dos_ising8"] = time_to_dos_small(rewl, range(1, 21),
+            legs["time_to_dos_ising8"] = time_to_dos(rewl, range(1, 21),
                                                           min(30.0, budget.left() - 15))
             t = legs["time_to_dos_ising8"]
             log(f"time-to-DOS 8x8 Ising: plain alone p50 {t['plain']['p50_s']:.3f} s p99 "
