@@ -128,10 +128,15 @@ __attribute__((target("fma"))) static double horner_hw(double Q, double z, doubl
     return __builtin_fma(Q, z, c);
 }
 static double horner_sw(double Q, double z, double c) { return fma(Q, z, c); }
-static int have_fma = -1;
+/* set once when the library is loaded, before any thread reads it */
+static int have_fma = 0;
+__attribute__((constructor)) static void detect_fma(void)
+{
+    __builtin_cpu_init();
+    have_fma = __builtin_cpu_supports("fma") ? 1 : 0;
+}
 static double horner(double Q, double z, double c)
 {
-    if (have_fma < 0) have_fma = __builtin_cpu_supports("fma") ? 1 : 0;
     return have_fma ? horner_hw(Q, z, c) : horner_sw(Q, z, c);
 }
 #else
